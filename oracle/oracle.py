@@ -1,0 +1,216 @@
+"""ctypes binding of the FP64 oracle (test infrastructure only).
+
+Interior layout of whole fields (x fastest):
+  cells (nz, ny, nx); Bx (nz, ny, nx+1); By (nz, ny+1, nx); Bz (nz+1, ny, nx),
+  in 2D nz = 1 and Bz is a cell array.
+Banded layout (the oracle's own patch storage): the same with every active
+axis extended by the band g on both sides.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+FIELDS = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_last_error.restype = C.c_char_p
+        L.orc_minmod.restype = C.c_double
+        L.orc_minmod.argtypes = [C.c_double, C.c_double]
+        L.orc_fast_speed.restype = C.c_double
+        L.orc_fast_speed.argtypes = [C.c_double] * 5
+        L.orc_uniform_time.restype = C.c_double
+        L.orc_dt_banded.restype = C.c_double
+        L.orc_max_threads.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _err():
+    return lib().orc_last_error().decode()
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _ptrs(arrs):
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in arrs]
+    pp = (_dp * len(keep))(*[k.ctypes.data_as(_dp) for k in keep])
+    return keep, pp
+
+
+def _ivec(v):
+    v = list(v) + [1] * (3 - len(v))
+    return (C.c_int * 3)(*[int(x) for x in v])
+
+
+def _dvec(v):
+    v = list(v) + [1.0] * (3 - len(v))
+    return (C.c_double * 3)(*[float(x) for x in v])
+
+
+def interior_shapes(ndim, n):
+    nx, ny = n[0], n[1]
+    nz = n[2] if ndim == 3 else 1
+    cell = (nz, ny, nx)
+    return [cell] * 5 + [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx) if ndim == 3 else cell]
+
+
+def banded_shapes(ndim, n, g):
+    nx, ny = n[0], n[1]
+    nz = n[2] if ndim == 3 else 1
+    gz = g if ndim == 3 else 0
+    cell = (nz + 2 * gz, ny + 2 * g, nx + 2 * g)
+    bz = (nz + 2 * gz + 1, ny + 2 * g, nx + 2 * g) if ndim == 3 else cell
+    return [cell] * 5 + [(cell[0], cell[1], cell[2] + 1), (cell[0], cell[1] + 1, cell[2]), bz]
+
+
+# ------------------------------------------------------------ pointwise pieces
+def minmod(a, b):
+    return lib().orc_minmod(float(a), float(b))
+
+
+def prim_to_cons(W, gamma):
+    W, pw = _arr(W)
+    U = np.zeros(8)
+    lib().orc_prim_to_cons(pw, U.ctypes.data_as(_dp), C.c_double(gamma))
+    return U
+
+
+def cons_to_prim(U, gamma):
+    U, pu = _arr(U)
+    W = np.zeros(8)
+    lib().orc_cons_to_prim(pu, W.ctypes.data_as(_dp), C.c_double(gamma))
+    return W
+
+
+def phys_flux(W, d, gamma):
+    W, pw = _arr(W)
+    F = np.zeros(8)
+    lib().orc_phys_flux(pw, C.c_int(d), C.c_double(gamma), F.ctypes.data_as(_dp))
+    return F
+
+
+def fast_speed(rho, p, B2, Bn, gamma):
+    return lib().orc_fast_speed(rho, p, B2, Bn, gamma)
+
+
+def hlld(L, R, gamma):
+    """HLLD flux of rotated primitive states (rho, un, ut1, ut2, p, Bn, Bt1, Bt2).
+    Returns (F[7], info) with info = (region, degen_L, degen_R, degen_double_star)."""
+    L, pl = _arr(L)
+    R, pr = _arr(R)
+    F = np.zeros(7)
+    info = (C.c_int * 4)()
+    lib().orc_hlld(pl, pr, C.c_double(gamma), F.ctypes.data_as(_dp), info)
+    return F, tuple(info)
+
+
+# ------------------------------------------------------------------- runs
+def uniform_run(ic, gamma, cfl, nsteps, g=2, fill_every=1, bc=(0, 0, 0), dts=None):
+    """Run a single uniform grid for nsteps.  Returns (fields[8], dts)."""
+    ndim, n = ic["ndim"], ic["n"]
+    keep1, pp = _ptrs(ic["prim"])
+    keep2, pb = _ptrs(ic["b"])
+    outs = [np.zeros(s) for s in interior_shapes(ndim, n)]
+    keep3, po = _ptrs(outs)
+    dts_out = np.zeros(max(nsteps, 1))
+    if dts is not None:
+        dts_in = np.ascontiguousarray(dts, dtype=np.float64)
+        pin = dts_in.ctypes.data_as(_dp)
+    else:
+        pin = None
+    rc = lib().orc_uniform_run(C.c_int(ndim), _ivec(n), _ivec(bc), C.c_double(gamma), C.c_double(cfl),
+                               _dvec(ic["dx"]), C.c_int(g), C.c_int(fill_every), C.c_int(nsteps), pin, pp, pb, po,
+                               dts_out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise RuntimeError("oracle uniform_run: " + _err())
+    return keep3, dts_out[:nsteps]
+
+
+def uniform_time(ic, gamma, cfl, nsteps, g=2, fill_every=1, bc=(0, 0, 0), threads=None):
+    """Wall seconds of nsteps of the uniform run (set-up excluded)."""
+    if threads:
+        lib().orc_set_threads(int(threads))
+    ndim, n = ic["ndim"], ic["n"]
+    keep1, pp = _ptrs(ic["prim"])
+    keep2, pb = _ptrs(ic["b"])
+    t = lib().orc_uniform_time(C.c_int(ndim), _ivec(n), _ivec(bc), C.c_double(gamma), C.c_double(cfl),
+                               _dvec(ic["dx"]), C.c_int(g), C.c_int(fill_every), C.c_int(nsteps), pp, pb)
+    if t < 0:
+        raise RuntimeError("oracle uniform_time: " + _err())
+    return t
+
+
+def max_threads():
+    return lib().orc_max_threads()
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
+
+
+# ---------------------------------------------------------- banded patches
+def step_banded(ndim, n, g, gv, gamma, dx, dt, fields):
+    keep, pin = _ptrs(fields)
+    outs = [np.zeros_like(f) for f in keep]
+    keep2, pout = _ptrs(outs)
+    rc = lib().orc_step_banded(C.c_int(ndim), _ivec(n), C.c_int(g), C.c_int(gv), C.c_double(gamma), _dvec(dx),
+                               C.c_double(dt), pin, pout)
+    if rc != 0:
+        raise RuntimeError("oracle step_banded: " + _err())
+    return keep2
+
+
+def fill_banded(ndim, n, g, bc, fields):
+    keep, pf = _ptrs(fields)
+    rc = lib().orc_fill_banded(C.c_int(ndim), _ivec(n), C.c_int(g), _ivec(bc), pf)
+    if rc != 0:
+        raise RuntimeError("oracle fill_banded: " + _err())
+    return keep
+
+
+def dt_banded(ndim, n, g, gamma, cfl, dx, fields):
+    keep, pf = _ptrs(fields)
+    return lib().orc_dt_banded(C.c_int(ndim), _ivec(n), C.c_int(g), C.c_double(gamma), C.c_double(cfl), _dvec(dx),
+                               pf)
+
+
+def banded_from_interior(ndim, n, g, fields):
+    """Place interior-layout conserved fields into banded arrays (band zero)."""
+    out = [np.zeros(s) for s in banded_shapes(ndim, n, g)]
+    gz = g if ndim == 3 else 0
+    for s in range(8):
+        f = np.asarray(fields[s])
+        out[s][gz:gz + f.shape[0], g:g + f.shape[1], g:g + f.shape[2]] = f
+    return out
+
+
+def interior_from_banded(ndim, n, g, fields):
+    shapes = interior_shapes(ndim, n)
+    gz = g if ndim == 3 else 0
+    return [np.array(fields[s][gz:gz + shapes[s][0], g:g + shapes[s][1], g:g + shapes[s][2]]) for s in range(8)]
+
+
+def conserved_interior(ic, gamma):
+    """The initial conserved state of an input set, as the oracle builds it
+    (zero steps of a uniform run)."""
+    f, _ = uniform_run(ic, gamma, 0.4, 0, g=2)
+    return f

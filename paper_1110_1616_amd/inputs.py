@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module only draws random numbers and samples analytic fields; it holds
+none of the scheme's arithmetic (no conserved variables, no fluxes, no
+averaging of data between levels).  Every field is produced in float64 in the
+"interior layout":
+
+* cells  : shape (nz, ny, nx), x fastest
+* Bx face: (nz, ny, nx+1), By face: (nz, ny+1, nx), Bz face: (nz+1, ny, nx)
+* in 2D nz = 1 and Bz is a cell array (1, ny, nx)
+
+Recipe for the smooth random fields (the paper's workloads are unspecified
+magnetised flows; these stand in for them):
+
+* mode sum f(x) = sum_{m<8} cos(2 pi k_m . x + phi_m), k_m integer in
+  [-4, 4]^ndim (k != 0), phi_m uniform in [0, 2 pi);
+* rho = 1 + 0.1 f (optionally times 4 on 0.25 <= x < 0.75), p = 1;
+* v = curl Psi (analytic, independent modes, random 3-vector amplitudes),
+  rescaled to a target rms |v|;
+* B = discrete curl of a vector potential A (independent modes, random unit
+  3-vector amplitudes) sampled at edge centres, so the face field is
+  divergence-free up to rounding; rescaled to a target rms of the
+  face-averaged field.  A is sampled at wrapped positions so that the face at
+  index n equals the face at index 0 bit for bit on periodic domains.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+def _modes(rng, ndim, nmodes=8, kmax=4):
+    ks = []
+    while len(ks) < nmodes:
+        k = rng.integers(-kmax, kmax + 1, size=ndim)
+        if np.any(k != 0):
+            ks.append(k)
+    k3 = np.zeros((nmodes, 3))
+    k3[:, :ndim] = np.array(ks, dtype=np.float64)
+    phi = rng.uniform(0.0, TWO_PI, size=nmodes)
+    return k3, phi
+
+
+def _unit3(rng, n):
+    a = rng.normal(size=(n, 3))
+    return a / np.linalg.norm(a, axis=1, keepdims=True)
+
+
+def _grid(xs, ys, zs):
+    z, y, x = np.meshgrid(zs, ys, xs, indexing="ij")
+    return x, y, z
+
+
+def _phase(k3, phi, x, y, z):
+    return TWO_PI * (k3[0] * x + k3[1] * y + k3[2] * z) + phi
+
+
+class _Field:
+    """Random smooth fields on the unit periodic box."""
+
+    def __init__(self, rng, ndim):
+        self.ndim = ndim
+        self.k_rho, self.phi_rho = _modes(rng, ndim)
+        self.k_psi, self.phi_psi = _modes(rng, ndim)
+        self.a_psi = _unit3(rng, 8)
+        self.k_a, self.phi_a = _modes(rng, ndim)
+        self.a_a = _unit3(rng, 8)
+
+    def f_rho(self, x, y, z):
+        out = np.zeros_like(x)
+        for m in range(8):
+            out += np.cos(_phase(self.k_rho[m], self.phi_rho[m], x, y, z))
+        return out
+
+    def curl_psi(self, x, y, z):
+        """Analytic curl of Psi = sum_m a_m cos(theta_m): -sum_m sin(theta_m) 2 pi (k_m x a_m)."""
+        v = [np.zeros_like(x) for _ in range(3)]
+        for m in range(8):
+            s = np.sin(_phase(self.k_psi[m], self.phi_psi[m], x, y, z))
+            c = np.cross(TWO_PI * self.k_psi[m], self.a_psi[m])
+            for a in range(3):
+                v[a] -= s * c[a]
+        return v
+
+    def pot(self, comp, x, y, z):
+        out = np.zeros_like(x)
+        for m in range(8):
+            out += self.a_a[m, comp] * np.cos(_phase(self.k_a[m], self.phi_a[m], x, y, z))
+        return out
+
+
+def _wrap_pos(n, count, offset, lo=0, h=None):
+    """Positions (index + offset) * h of `count` consecutive indices starting
+    at lo, with the index wrapped into [0, n) so periodic images coincide."""
+    h = 1.0 / n if h is None else h
+    idx = (np.arange(lo, lo + count) % n).astype(np.float64)
+    return (idx + offset) * h
+
+
+def curl_faces(ndim, n, pot):
+    """Face B from the discrete curl of A sampled at edge centres.
+
+    pot(comp, x, y, z) evaluates component comp of A.  Returns (bx, by, bz) in
+    the interior layout.  This is input construction (a discrete curl of a
+    sampled potential), not part of the scheme."""
+    nx, ny = n[0], n[1]
+    dx, dy = 1.0 / nx, 1.0 / ny
+    if ndim == 2:
+        # A_z at nodes, A_x at y-faces, A_y at x-faces.
+        x, y, z = _grid(_wrap_pos(nx, nx + 1, 0.0), _wrap_pos(ny, ny + 1, 0.0), np.zeros(1))
+        az = pot(2, x, y, z)[0]
+        x, y, z = _grid(_wrap_pos(nx, nx, 0.5), _wrap_pos(ny, ny + 1, 0.0), np.zeros(1))
+        ax = pot(0, x, y, z)[0]
+        x, y, z = _grid(_wrap_pos(nx, nx + 1, 0.0), _wrap_pos(ny, ny, 0.5), np.zeros(1))
+        ay = pot(1, x, y, z)[0]
+        bx = (az[1:, :] - az[:-1, :]) / dy
+        by = -(az[:, 1:] - az[:, :-1]) / dx
+        bz = (ay[:, 1:] - ay[:, :-1]) / dx - (ax[1:, :] - ax[:-1, :]) / dy
+        return bx[None], by[None], bz[None]
+    nz = n[2]
+    dz = 1.0 / nz
+    # A_x at x-edges ((i+1/2)dx, j dy, k dz)
+    x, y, z = _grid(_wrap_pos(nx, nx, 0.5), _wrap_pos(ny, ny + 1, 0.0), _wrap_pos(nz, nz + 1, 0.0))
+    ax = pot(0, x, y, z)
+    x, y, z = _grid(_wrap_pos(nx, nx + 1, 0.0), _wrap_pos(ny, ny, 0.5), _wrap_pos(nz, nz + 1, 0.0))
+    ay = pot(1, x, y, z)
+    x, y, z = _grid(_wrap_pos(nx, nx + 1, 0.0), _wrap_pos(ny, ny + 1, 0.0), _wrap_pos(nz, nz, 0.5))
+    az = pot(2, x, y, z)
+    bx = (az[:, 1:, :] - az[:, :-1, :]) / dy - (ay[1:, :, :] - ay[:-1, :, :]) / dz
+    by = (ax[1:, :, :] - ax[:-1, :, :]) / dz - (az[:, :, 1:] - az[:, :, :-1]) / dx
+    bz = (ay[:, :, 1:] - ay[:, :, :-1]) / dx - (ax[:, 1:, :] - ax[:, :-1, :]) / dy
+    return bx, by, bz
+
+
+def _face_mean_sq(ndim, b):
+    """Mean over cells of |face-averaged B|^2 (used only to set an amplitude)."""
+    bx, by, bz = b
+    s = (0.5 * (bx[:, :, 1:] + bx[:, :, :-1])) ** 2 + (0.5 * (by[:, 1:, :] + by[:, :-1, :])) ** 2
+    if ndim == 3:
+        s = s + (0.5 * (bz[1:] + bz[:-1])) ** 2
+    else:
+        s = s + bz ** 2
+    return float(np.mean(s))
+
+
+def smooth_mhd(ndim, n, seed, v_rms=0.1, b_rms=0.1, rho_amp=0.1, jump=False, p0=1.0):
+    """Smooth seeded MHD state on the unit periodic box.
+
+    Returns dict(prim=[rho, vx, vy, vz, p], b=[bx, by, bz], dx=[...]) in the
+    interior layout."""
+    n = tuple(int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    fld = _Field(rng, ndim)
+    nx, ny = n[0], n[1]
+    nz = n[2] if ndim == 3 else 1
+    xs = (np.arange(nx) + 0.5) / nx
+    ys = (np.arange(ny) + 0.5) / ny
+    zs = (np.arange(nz) + 0.5) / nz if ndim == 3 else np.zeros(1)
+    x, y, z = _grid(xs, ys, zs)
+    rho = 1.0 + rho_amp * fld.f_rho(x, y, z)
+    if jump:
+        rho = np.where((x >= 0.25) & (x < 0.75), 4.0 * rho, rho)
+    v = fld.curl_psi(x, y, z)
+    vr = np.sqrt(np.mean(v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
+    v = [c * (v_rms / vr) for c in v]
+    p = np.full_like(rho, p0)
+    b = list(curl_faces(ndim, n, fld.pot))
+    scale = b_rms / np.sqrt(_face_mean_sq(ndim, b))
+    b = [c * scale for c in b]
+    dx = [1.0 / nx, 1.0 / ny, 1.0 / nz if ndim == 3 else 1.0]
+    return {"prim": [rho, v[0], v[1], v[2], p], "b": b, "dx": dx, "ndim": ndim, "n": n}
+
+
+def uniform_state(ndim, n, rho=1.0, v=(0.1, -0.05, 0.02), p=1.0, B=(0.3, 0.2, -0.1)):
+    """Spatially uniform state (every cell and face equal)."""
+    nx, ny = n[0], n[1]
+    nz = n[2] if ndim == 3 else 1
+    shp = (nz, ny, nx)
+    prim = [np.full(shp, float(rho)), np.full(shp, float(v[0])), np.full(shp, float(v[1])),
+            np.full(shp, float(v[2])), np.full(shp, float(p))]
+    bx = np.full((nz, ny, nx + 1), float(B[0]))
+    by = np.full((nz, ny + 1, nx), float(B[1]))
+    bz = np.full((nz + 1, ny, nx) if ndim == 3 else shp, float(B[2]))
+    dx = [1.0 / nx, 1.0 / ny, 1.0 / nz if ndim == 3 else 1.0]
+    return {"prim": prim, "b": [bx, by, bz], "dx": dx, "ndim": ndim, "n": tuple(n)}
+
+
+def alfven_wave(ndim, N, amp=1e-6, gamma=5.0 / 3.0):
+    """Linear Alfven wave on the unit box: B0 parallel to k, |B0| = 1, rho = 1,
+    p = 1/gamma (so v_A = 1, omega = |k|); dB = amp e sin(k.x), dv = -dB.
+    k = 2 pi (1, 2) with e = z in 2D; k = 2 pi (1, 1, 2) with e = (1,-1,0)/sqrt2
+    in 3D, dB from its vector potential (amp/|k|^2)(k x e) cos(k.x)."""
+    if ndim == 2:
+        kv = np.array([1.0, 2.0, 0.0])
+        e = np.array([0.0, 0.0, 1.0])
+        n = (N, N)
+    else:
+        kv = np.array([1.0, 1.0, 2.0])
+        e = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+        n = (N, N, N)
+    k = TWO_PI * kv
+    khat = kv / np.linalg.norm(kv)
+    B0 = khat
+    nx, ny = n[0], n[1]
+    nz = n[2] if ndim == 3 else 1
+    xs = (np.arange(nx) + 0.5) / nx
+    ys = (np.arange(ny) + 0.5) / ny
+    zs = (np.arange(nz) + 0.5) / nz if ndim == 3 else np.zeros(1)
+    x, y, z = _grid(xs, ys, zs)
+    th = k[0] * x + k[1] * y + k[2] * z
+    dB = [amp * e[a] * np.sin(th) for a in range(3)]
+    prim = [np.ones_like(x), -dB[0], -dB[1], -dB[2], np.full_like(x, 1.0 / gamma)]
+    a_vec = np.cross(k, e) * (amp / np.dot(k, k))
+
+    def pot(comp, xx, yy, zz):
+        return a_vec[comp] * np.cos(k[0] * xx + k[1] * yy + k[2] * zz)
+
+    if ndim == 3:
+        bx, by, bz = curl_faces(3, n, pot)
+        bx = bx + B0[0]
+        by = by + B0[1]
+        bz = bz + B0[2]
+    else:
+        bx = np.full((1, ny, nx + 1), B0[0])
+        by = np.full((1, ny + 1, nx), B0[1])
+        bz = dB[2].copy()
+    dx = [1.0 / nx, 1.0 / ny, 1.0 / nz if ndim == 3 else 1.0]
+    return {"prim": prim, "b": [bx, by, bz], "dx": dx, "ndim": ndim, "n": n, "omega": float(np.linalg.norm(k))}
+
+
+def brio_wu(N, ny=4):
+    """Brio & Wu (1988) shock tube along x on [0,1] x [0, ny/N): gamma = 2,
+    left (rho, p, By) = (1, 1, 1), right (0.125, 0.1, -1), Bx = 0.75, v = 0."""
+    nx = N
+    xs = (np.arange(nx) + 0.5) / nx
+    left = xs < 0.5
+    shp = (1, ny, nx)
+    rho = np.broadcast_to(np.where(left, 1.0, 0.125), shp).copy()
+    p = np.broadcast_to(np.where(left, 1.0, 0.1), shp).copy()
+    zero = np.zeros(shp)
+    bx = np.full((1, ny, nx + 1), 0.75)
+    by = np.broadcast_to(np.where(left, 1.0, -1.0), (1, ny + 1, nx)).copy()
+    bz = np.zeros(shp)
+    dx = [1.0 / nx, 1.0 / nx, 1.0]
+    return {"prim": [rho, zero.copy(), zero.copy(), zero.copy(), p], "b": [bx, by, bz], "dx": dx, "ndim": 2,
+            "n": (nx, ny)}
+
+
+def advected_profile(N, seed=7, v=(0.37, 0.0, 0.0), p=1.0, B=(0.0, 0.0, 0.0), ndim=2, ny=4):
+    """Density profile rho(x) = 1 + 0.5 sum of 3 random x-modes, advected at
+    constant v, p and B (a contact discontinuity problem along x)."""
+    rng = np.random.default_rng(seed)
+    nx = N
+    xs = (np.arange(nx) + 0.5) / nx
+    ks = rng.integers(1, 5, size=3)
+    ph = rng.uniform(0.0, TWO_PI, size=3)
+    prof = 1.0 + 0.5 * sum(np.cos(TWO_PI * ks[m] * xs + ph[m]) for m in range(3)) / 3.0
+    if ndim == 2:
+        shp = (1, ny, nx)
+        n = (nx, ny)
+    else:
+        shp = (ny, ny, nx)
+        n = (nx, ny, ny)
+    rho = np.broadcast_to(prof, shp).copy()
+    u = uniform_state(ndim, n, 1.0, v, p, B)
+    u["prim"][0] = rho
+    u["dx"] = [1.0 / nx, 1.0 / nx, 1.0 / nx if ndim == 3 else 1.0]
+    return u
