@@ -1,0 +1,188 @@
+"""Benchmark of the batched MHD patch advance on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+Prints ONE JSON line.  `value` is useful cell-updates per second (one
+interior cell advanced by one (sub)step) of the whole step with inputs
+resident in HBM; the roofline object reports the dominant kernel (the flux
+kernel: primitive recovery, minmod slopes, Hancock predictor and HLLD) against
+the FP64 vector peak, its duration measured live with HIP events on the
+launch stream.  cpu_baseline times the FP64 oracle on a bounded sample of the
+same workload on the host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X FP64 vector
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector (packed); the kernels do not use packed FP32
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work of the flux kernel, counted by running the oracle's own
+# step on a flop-counting scalar (each +, -, *, /, sqrt = 1): Hancock
+# predictor phase (primitive recovery, minmod slopes, face states, half-step
+# increment, predicted states) per cell whose predicted states are formed,
+# and one HLLD evaluation per face.  Checked against the oracle by a test.
+FLOPS_PRED = {3: 912, 2: 612}
+FLOPS_HLLD = 367
+GAMMA = 5.0 / 3.0
+
+
+def flux_kernel_flops(ndim, n, gv):
+    """Algorithmic flops of one flux-kernel launch over a grid with interior n
+    (per axis) advanced from valid band gv."""
+    m = [x + 2 * gv - 2 for x in n[:ndim]]  # cells with predicted states
+    cells = 1
+    for x in m:
+        cells *= x
+    faces = 0
+    for d in range(ndim):
+        f = m[d] - 1
+        for a in range(ndim):
+            if a != d:
+                f *= m[a]
+        faces += f
+    return FLOPS_PRED[ndim] * cells + FLOPS_HLLD * faces
+
+
+def single_grid_workload(args):
+    import numpy as np
+    import torch
+
+    from paper_1110_1616_amd import amr as A
+    from paper_1110_1616_amd import inputs as I
+
+    N = args.n
+    dtype = args.dtype
+    n = (N, N, N)
+    ic = I.smooth_mhd(3, n, seed=2, v_rms=0.1, b_rms=0.3, jump=True)
+    H = A.Hierarchy(3, n, [(0, (0, 0, 0), n)], ghost=4, dtype=dtype, dx0=ic["dx"], gamma=GAMMA, cfl=0.4)
+    U, V = H.new_state(), H.new_state()
+    H.load_primitive(U, 0, ic["prim"], ic["b"])
+    state = {"U": U, "V": V, "s": 0}
+
+    def step():
+        # one step of the single grid: band 4 is refilled every second step
+        # (the two-substep patch mode), dt from the CFL reduction, advance
+        s = state["s"]
+        band = 4 if s % 2 == 0 else 2
+        if band == 4:
+            H.fill(0, A.AMR_FILL_FULL, state["U"])
+        H.compute_dt(state["U"])
+        H.advance(state["U"], state["V"], cycle=0, band=band)
+        state["U"], state["V"] = state["V"], state["U"]
+        state["s"] = s + 1
+
+    flops_per_step_pair = flux_kernel_flops(3, n, 4) + flux_kernel_flops(3, n, 2)
+    info = {
+        "workload": f"single 3D grid {N}^3 + 4-cell band, ideal MHD {dtype}, smooth Fourier-mode rho/v/A "
+                    f"(|B| rms 0.3) with a 4:1 planar density jump, periodic, CFL 0.4",
+        "cells": N ** 3,
+        "ndim": 3,
+        "dtype": dtype,
+        "grids": 1,
+    }
+
+    def cpu_sample():
+        import oracle as O
+        steps = args.cpu_steps
+        t = O.uniform_time(ic, GAMMA, 0.4, steps, g=4, fill_every=2)
+        return {"seconds": t, "updates": float(N ** 3 * steps), "threads": O.max_threads(),
+                "sample": f"oracle, same {N}^3 input, first {steps} steps (band 4 refilled every 2 steps)"}
+
+    return H, step, (lambda k: flops_per_step_pair * k / 2.0), info, cpu_sample
+
+
+WORKLOADS = {"single128": single_grid_workload}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="single128", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(it shards by grid in design only); rerun with --gpus 1", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1110_1616_amd import amr as A
+
+    torch.cuda.set_device(0)
+    H, step, flux_flops, info, cpu_sample = WORKLOADS[args.workload](args)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    A.amr_set_kernel_timing(H.h, True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    flux_ms, upd_ms, nl = A.amr_kernel_times(H.h)
+    A.amr_set_kernel_timing(H.h, False)
+    flags, _ = H.error_flags()
+    if flags:
+        print("non-physical state flagged during the benchmark", file=sys.stderr)
+        sys.exit(3)
+
+    seconds = gpu_ms / 1e3
+    updates = float(info["cells"]) * args.steps
+    value = updates / seconds
+    fl = flux_flops(args.steps)
+    peak = PEAK_FP64_VECTOR_TFLOPS if info["dtype"] == "f64" else PEAK_FP32_VECTOR_TFLOPS
+    achieved = fl / (flux_ms / 1e3) / 1e12
+    esize = 8 if info["dtype"] == "f64" else 4
+    out = {
+        "metric": "MHD cell-updates/s (useful interior cell-updates per second of the batched advance)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": info["dtype"],
+        "data": "synthetic",
+        "config": {"workload": info["workload"], "grids": info["grids"], "cells": info["cells"],
+                   "parallelism": "single GPU"},
+        "roofline": {"kernel": "k_flux", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "avg_launch_ms": flux_ms / max(nl, 1), "launches": nl},
+        "kernels_ms_per_step": {"k_flux": flux_ms / args.steps, "k_update": upd_ms / args.steps},
+        "hbm_algorithmic_GBps": updates * 16 * esize / seconds / 1e9,
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        cs = cpu_sample()
+        out["cpu_baseline"] = {"value": cs["updates"] / cs["seconds"], "unit": "cell-updates/s",
+                               "cores": cs["threads"], "kind": "oracle", "sample": cs["sample"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

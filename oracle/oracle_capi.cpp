@@ -290,3 +290,97 @@ double orc_dt_banded(int ndim, const int* n, int g, double gamma, double cfl, co
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ flop counts
+// A scalar that counts its arithmetic (+, -, *, /, sqrt each one flop) so the
+// algorithmic work of the scheme's pieces can be read off the oracle itself.
+namespace {
+struct Cnt {
+  double v;
+  static long long n;
+  Cnt(double x = 0.0) : v(x) {}
+};
+long long Cnt::n = 0;
+inline Cnt operator+(const Cnt& a, const Cnt& b) { ++Cnt::n; return Cnt(a.v + b.v); }
+inline Cnt operator-(const Cnt& a, const Cnt& b) { ++Cnt::n; return Cnt(a.v - b.v); }
+inline Cnt operator*(const Cnt& a, const Cnt& b) { ++Cnt::n; return Cnt(a.v * b.v); }
+inline Cnt operator/(const Cnt& a, const Cnt& b) { ++Cnt::n; return Cnt(a.v / b.v); }
+inline Cnt operator-(const Cnt& a) { return Cnt(-a.v); }
+inline Cnt operator*(double a, const Cnt& b) { ++Cnt::n; return Cnt(a * b.v); }
+inline Cnt operator*(const Cnt& a, double b) { ++Cnt::n; return Cnt(a.v * b); }
+inline Cnt operator/(const Cnt& a, double b) { ++Cnt::n; return Cnt(a.v / b); }
+inline Cnt operator/(double a, const Cnt& b) { ++Cnt::n; return Cnt(a / b.v); }
+inline Cnt operator+(const Cnt& a, double b) { ++Cnt::n; return Cnt(a.v + b); }
+inline Cnt operator-(const Cnt& a, double b) { ++Cnt::n; return Cnt(a.v - b); }
+inline Cnt operator-(double a, const Cnt& b) { ++Cnt::n; return Cnt(a - b.v); }
+// found by argument-dependent lookup from the templated scheme
+inline double value(const Cnt& x) { return x.v; }
+inline Cnt Sqrt(const Cnt& x) { ++Cnt::n; return Cnt(std::sqrt(x.v)); }
+}  // namespace
+long long g_marks[4];
+namespace orc {
+template <> struct OmpSafe<Cnt> { static constexpr bool value = false; };
+template <> struct StepMark<Cnt> {
+  static void mark(int k) { g_marks[k] = Cnt::n; }
+};
+}  // namespace orc
+
+extern "C" {
+
+// Flop counts of one step on an n^ndim periodic patch with band 2 of a
+// smooth state (every HLLD face takes the double-star path in practice).
+// out[0] = total flops of the step, out[1] = cells updated, out[2] = cells
+// whose predicted states were formed, out[3] = HLLD faces evaluated,
+// out[4..7] = flops of the phases: primitives + slopes + predictor, HLLD
+// fluxes, EMFs, update.
+int orc_count_step_flops(int ndim, int n, double* out) {
+  try {
+    int nn[3] = {n, n, n};
+    Layout L = make_layout(ndim, nn, 2);
+    State<Cnt> S(L), O(L);
+    // smooth state: rho ~ 1, small v, p = 1, B ~ 0.3 with a gentle variation
+    for (int s = 0; s < NVAR; ++s)
+      for (size_t e = 0; e < L.fsize(s); ++e) {
+        double x = 0.37 * (double)e;
+        double v = 0.0;
+        switch (s) {
+          case 0: v = 1.0 + 0.05 * std::sin(x); break;
+          case 1: v = 0.05 * std::sin(1.3 * x); break;
+          case 2: v = 0.05 * std::cos(0.7 * x); break;
+          case 3: v = 0.04 * std::sin(0.9 * x); break;
+          case 4: v = 2.0 + 0.02 * std::cos(x); break;
+          case 5: v = 0.3; break;
+          case 6: v = 0.2 + 0.01 * std::sin(0.5 * x); break;
+          default: v = -0.1; break;
+        }
+        S.f[s][e] = Cnt(v);
+      }
+    StepParams P{5.0 / 3.0, {1.0 / n, 1.0 / n, 1.0 / n}};
+    Cnt::n = 0;
+    step(S, O, 2, Cnt(1e-4), P);
+    long long m = n + 2;  // cells with predicted states per axis: [-1, n+1)
+    out[0] = (double)Cnt::n;
+    out[1] = std::pow((double)n, ndim);
+    out[2] = std::pow((double)m, ndim);
+    out[3] = (double)ndim * (double)(n + 1) * std::pow((double)m, ndim - 1);
+    out[4] = (double)g_marks[1];
+    out[5] = (double)(g_marks[2] - g_marks[1]);
+    out[6] = (double)(g_marks[3] - g_marks[2]);
+    out[7] = (double)(Cnt::n - g_marks[3]);
+    return 0;
+  } catch (const std::exception& e) {
+    return fail(e.what());
+  }
+}
+
+// Flops of one HLLD evaluation on a generic state (double-star path).
+long long orc_count_hlld_flops() {
+  Cnt L[8] = {1.0, 0.05, 0.02, -0.01, 1.0, 0.3, 0.2, -0.1};
+  Cnt R[8] = {0.9, 0.04, 0.01, 0.0, 0.95, 0.3, 0.25, -0.05};
+  Cnt F[7];
+  Cnt::n = 0;
+  hlld(L, R, 5.0 / 3.0, F);
+  return Cnt::n;
+}
+
+}  // extern "C"

@@ -32,6 +32,12 @@ namespace orc {
 // that record a global tape set this to false.
 template <class T> struct OmpSafe { static constexpr bool value = true; };
 
+// Phase marks of one step (used only by the flop-counting scalar to split
+// the step's work into its parts; a no-op for every other type).
+template <class T> struct StepMark {
+  static void mark(int) {}
+};
+
 // ---------------------------------------------------------------- scalar glue
 inline double value(double x) { return x; }
 inline double Sqrt(double x) { return std::sqrt(x); }
@@ -427,6 +433,7 @@ void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P) 
       }
 
   if (bad) throw NonPhysical("non-positive density or pressure");
+  StepMark<T>::mark(1);
 
   // (5) HLLD fluxes.  Flux[d] at face index f (between cells f-1 and f along
   // d) is stored at the cell index of its high-side cell.  Lab-frame slots.
@@ -469,6 +476,7 @@ void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P) 
           F[5 + tdir(d, 2)] = fr[6];
         }
   }
+  StepMark<T>::mark(2);
   auto FX = [&](int d, int s, int i, int j, int k) -> const T& {
     return Flux[((size_t)d * ncell + cid(i, j, k)) * NVAR + s];
   };
@@ -510,6 +518,7 @@ void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P) 
         }
   }
 
+  StepMark<T>::mark(3);
   // (7) update cells [-gv+2, n+gv-2).
   const int ncons = nd == 2 ? 6 : 5;  // in 2D Bz (slot 7) is a cell quantity
 #pragma omp parallel for collapse(2) if (OMP_OK)

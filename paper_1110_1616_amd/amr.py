@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libamrmhd.so (include/amr.h).
+
+Argument marshalling only: every step of the advance runs in the library's
+HIP kernels.  PyTorch supplies device memory (the state pools and the
+workspace are torch tensors) and the stream (the current torch stream).
+There is no CPU fallback: if the library is missing this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamrmhd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "amr.h")
+
+AMR_OK, AMR_EINVAL, AMR_EHIP, AMR_ENOMEM, AMR_ESTATE, AMR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+AMR_F32, AMR_F64 = 0, 1
+AMR_BC_PERIODIC, AMR_BC_OUTFLOW = 0, 1
+AMR_FILL_FULL, AMR_FILL_SAME_LEVEL = 0, 1
+FIELDS = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
+
+
+class amr_grid(C.Structure):
+    _fields_ = [("level", C.c_int32), ("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+
+
+class amr_params(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nlevels", C.c_int32), ("ratio", C.c_int32), ("ghost", C.c_int32),
+                ("dtype", C.c_int32), ("bc", C.c_int32 * 3), ("domain", C.c_int32 * 3), ("dx0", C.c_double * 3),
+                ("gamma", C.c_double), ("cfl", C.c_double)]
+
+
+class amr_state(C.Structure):
+    _fields_ = [("f", C.c_void_p * 8)]
+
+
+class AmrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+_VP = C.c_void_p
+_PP = C.POINTER(C.c_void_p)
+
+
+def lib():
+    """Load libamrmhd.so (built in-tree by build()); raise if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        L.amr_last_error.restype = C.c_char_p
+        L.amr_strerror.restype = C.c_char_p
+        L.amr_create.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.POINTER(_VP)]
+        L.amr_destroy.argtypes = [_VP]
+        L.amr_layout.argtypes = [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.amr_load_primitive.argtypes = [_VP, C.c_int32, _PP, _PP, C.POINTER(amr_state), _VP]
+        L.amr_store_interior.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), _PP, _VP]
+        L.amr_compute_dt.argtypes = [_VP, C.POINTER(amr_state), _VP, _VP, _VP]
+        L.amr_fill_ghosts_prolong.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(amr_state), _VP]
+        L.amr_advance_patches.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                          C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP, _VP]
+        L.amr_restrict_fluxfix.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP]
+        L.amr_advance_adjoint.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
+                                          C.POINTER(amr_state), _VP, _VP]
+        L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+        L.amr_set_kernel_timing.argtypes = [_VP, C.c_int32]
+        L.amr_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        _LIB = L
+    return _LIB
+
+
+def header_functions():
+    """Names of the functions include/amr.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(amr_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(rc, what):
+    if rc != AMR_OK:
+        raise AmrError(rc, f"{what}: {lib().amr_last_error().decode()}")
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------- C names
+def amr_create(params, grids):
+    arr = (amr_grid * len(grids))(*grids)
+    h = C.c_void_p()
+    _check(lib().amr_create(C.byref(params), arr, len(grids), C.byref(h)), "amr_create")
+    return h
+
+
+def amr_destroy(h):
+    _check(lib().amr_destroy(h), "amr_destroy")
+
+
+def amr_layout(h, ngrids):
+    se = C.c_int64()
+    wb = C.c_int64()
+    offs = (C.c_int64 * ngrids)()
+    _check(lib().amr_layout(h, C.byref(se), C.byref(wb), offs), "amr_layout")
+    return se.value, wb.value, list(offs)
+
+
+def amr_load_primitive(h, grid, prim, b, U):
+    pp = (C.c_void_p * 5)(*[t.data_ptr() for t in prim])
+    bb = (C.c_void_p * 3)(*[t.data_ptr() for t in b])
+    _check(lib().amr_load_primitive(h, grid, pp, bb, C.byref(U), _stream()), "amr_load_primitive")
+
+
+def amr_store_interior(h, grid, U, outs):
+    oo = (C.c_void_p * 8)(*[t.data_ptr() for t in outs])
+    _check(lib().amr_store_interior(h, grid, C.byref(U), oo, _stream()), "amr_store_interior")
+
+
+def amr_compute_dt(h, U, dt0, ws):
+    _check(lib().amr_compute_dt(h, C.byref(U), _ptr(dt0), _ptr(ws), _stream()), "amr_compute_dt")
+
+
+def amr_fill_ghosts_prolong(h, level, mode, U):
+    _check(lib().amr_fill_ghosts_prolong(h, level, mode, C.byref(U), _stream()), "amr_fill_ghosts_prolong")
+
+
+def amr_advance_patches(h, cycle, subset, band, Uin, Uout, dt0, ws):
+    if subset:
+        arr = (C.c_int32 * len(subset))(*subset)
+        n = len(subset)
+    else:
+        arr, n = None, 0
+    _check(lib().amr_advance_patches(h, cycle, arr, n, band, C.byref(Uin), C.byref(Uout), _ptr(dt0), _ptr(ws),
+                                     _stream()), "amr_advance_patches")
+
+
+def amr_restrict_fluxfix(h, fine_level, Ufine, Ucoarse, ws):
+    _check(lib().amr_restrict_fluxfix(h, fine_level, C.byref(Ufine), C.byref(Ucoarse), _ptr(ws), _stream()),
+           "amr_restrict_fluxfix")
+
+
+def amr_advance_adjoint(h, grid_or_level, dts, Uck, lam, ws):
+    d = (C.c_double * len(dts))(*[float(x) for x in dts])
+    _check(lib().amr_advance_adjoint(h, grid_or_level, len(dts), d, C.byref(Uck), C.byref(lam), _ptr(ws),
+                                     _stream()), "amr_advance_adjoint")
+
+
+def amr_get_error_flags(h):
+    fl = C.c_uint32()
+    bad = C.c_int64()
+    rc = lib().amr_get_error_flags(h, C.byref(fl), C.byref(bad))
+    if rc not in (AMR_OK, AMR_ESTATE):
+        _check(rc, "amr_get_error_flags")
+    return fl.value, bad.value
+
+
+def amr_set_kernel_timing(h, enable):
+    _check(lib().amr_set_kernel_timing(h, int(bool(enable))), "amr_set_kernel_timing")
+
+
+def amr_kernel_times(h):
+    a, b, n = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().amr_kernel_times(h, C.byref(a), C.byref(b), C.byref(n)), "amr_kernel_times")
+    return a.value, b.value, n.value
+
+
+# ----------------------------------------------------------- convenience
+class State:
+    """Eight device pools (torch tensors) of one hierarchy state."""
+
+    def __init__(self, fields):
+        self.fields = fields
+        self.c = amr_state()
+        for i, t in enumerate(fields):
+            self.c.f[i] = t.data_ptr()
+
+    def copy_(self, other):
+        for a, b in zip(self.fields, other.fields):
+            a.copy_(b)
+        return self
+
+
+class Hierarchy:
+    """A grid hierarchy handle plus the torch-owned memory sized for it."""
+
+    def __init__(self, ndim, domain, grids, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0, 0), dx0=None,
+                 gamma=5.0 / 3.0, cfl=0.4, device="cuda"):
+        import torch
+        self.torch = torch
+        self.ndim = ndim
+        self.domain = tuple(domain) + (1,) * (3 - len(domain))
+        self.nlevels = nlevels
+        self.ratio = ratio
+        self.ghost = ghost
+        self.gamma = gamma
+        self.dtype = torch.float64 if dtype == "f64" else torch.float32
+        p = amr_params()
+        p.ndim, p.nlevels, p.ratio, p.ghost = ndim, nlevels, ratio, ghost
+        p.dtype = AMR_F64 if dtype == "f64" else AMR_F32
+        for d in range(3):
+            p.bc[d] = bc[d] if d < len(bc) else 0
+            p.domain[d] = self.domain[d]
+            p.dx0[d] = (dx0[d] if dx0 is not None else 1.0 / self.domain[d]) if d < ndim else 1.0
+        p.gamma, p.cfl = gamma, cfl
+        self.params = p
+        self.grid_records = []
+        for g in grids:
+            lev, lo, hi = g
+            lo = tuple(lo) + (0,) * (3 - len(lo))
+            hi = tuple(hi) + (1,) * (3 - len(hi))
+            self.grid_records.append(amr_grid(lev, (C.c_int32 * 3)(*lo), (C.c_int32 * 3)(*hi)))
+        self.grids = [(g.level, tuple(g.lo), tuple(g.hi)) for g in self.grid_records]
+        self.h = amr_create(p, self.grid_records)
+        self.state_elems, self.workspace_bytes, self.offsets = amr_layout(self.h, len(grids))
+        self.device = device
+        self.ws = torch.zeros(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+        self.dt0 = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                amr_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def new_state(self):
+        t = self.torch
+        return State([t.zeros(self.state_elems, dtype=self.dtype, device=self.device) for _ in range(8)])
+
+    def grid_shape(self, gi):
+        _, lo, hi = self.grids[gi]
+        n = [hi[d] - lo[d] for d in range(3)]
+        return n
+
+    def interior_shapes(self, gi):
+        nx, ny, nz = self.grid_shape(gi)
+        cell = (nz, ny, nx)
+        bz = (nz + 1, ny, nx) if self.ndim == 3 else cell
+        return [cell] * 5 + [(nz, ny, nx + 1), (nz, ny + 1, nx), bz]
+
+    def load_primitive(self, U, gi, prim, b):
+        t = self.torch
+        pd = [t.as_tensor(np.ascontiguousarray(a), dtype=t.float64, device=self.device) for a in prim]
+        bd = [t.as_tensor(np.ascontiguousarray(a), dtype=t.float64, device=self.device) for a in b]
+        amr_load_primitive(self.h, gi, pd, bd, U.c)
+        t.cuda.synchronize()
+
+    def store_interior(self, U, gi):
+        t = self.torch
+        outs = [t.zeros(s, dtype=t.float64, device=self.device) for s in self.interior_shapes(gi)]
+        amr_store_interior(self.h, gi, U.c, outs)
+        t.cuda.synchronize()
+        return [o.cpu().numpy() for o in outs]
+
+    def compute_dt(self, U):
+        amr_compute_dt(self.h, U.c, self.dt0, self.ws)
+
+    def fill(self, level, mode, U):
+        amr_fill_ghosts_prolong(self.h, level, mode, U.c)
+
+    def advance(self, Uin, Uout, cycle=0, band=0, subset=None):
+        amr_advance_patches(self.h, -1 if subset else cycle, subset, band, Uin.c, Uout.c, self.dt0, self.ws)
+
+    def error_flags(self):
+        return amr_get_error_flags(self.h)

@@ -1,0 +1,439 @@
+// Patch advance kernels for gfx950: the hot path of the hyperbolic step.
+//
+// One substep of a set of grids is two launches over a batched work list:
+//   k_flux   - per 16x16-thread column tile marching along z: primitive
+//              recovery, minmod slopes, Hancock half-step and HLLD fluxes on
+//              the tile's faces (a wave64 holds four 16-cell rows; x is the
+//              fastest index so global loads and stores are coalesced);
+//   k_update - conservative update of cells and CT update of faces from the
+//              face fluxes, with the edge EMFs formed from them.
+// Work lists hold tiles of any number of grids of any level; the kernels
+// read each tile's grid descriptor, so one launch covers every grid that
+// steps in a launch cycle.
+#include "amr_internal.hpp"
+#include "mhd_device.hpp"
+
+namespace amr {
+
+namespace {
+
+template <int NDIM> struct Idx {
+  int64_t base;  // element of cell (0,0,0)
+  int32_t sy, sz;
+  __device__ __forceinline__ Idx(const GridDesc& G) {
+    sy = G.P[0];
+    sz = G.P[0] * G.P[1];
+    base = G.off + G.g + (int64_t)G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0);
+  }
+  __device__ __forceinline__ int64_t operator()(int i, int j, int k) const {
+    return base + i + (int64_t)j * sy + (NDIM == 3 ? (int64_t)k * sz : 0);
+  }
+};
+
+// Primitive state of cell e (element index) from the conserved state and
+// the bounding faces.
+template <class T, int NDIM>
+__device__ __forceinline__ void load_prim(const DevState<T>& U, int64_t e, int32_t sy, int32_t sz, T gm1, T (&w)[8]) {
+  T u[8];
+  u[0] = U.f[0][e];
+  u[1] = U.f[1][e];
+  u[2] = U.f[2][e];
+  u[3] = U.f[3][e];
+  u[4] = U.f[4][e];
+  u[5] = T(0.5) * (U.f[5][e] + U.f[5][e + 1]);
+  u[6] = T(0.5) * (U.f[6][e] + U.f[6][e + sy]);
+  if (NDIM == 3)
+    u[7] = T(0.5) * (U.f[7][e] + U.f[7][e + sz]);
+  else
+    u[7] = U.f[7][e];
+  to_primitive(u, w, gm1);
+}
+
+__device__ __forceinline__ void flag_bad(ErrBlock* err, int64_t e) {
+  unsigned old = atomicOr(&err->flags, 1u);
+  if ((old & 1u) == 0u) atomicExch((unsigned long long*)&err->first_bad, (unsigned long long)e);
+}
+
+// Direction-d face states of one cell, Hancock-evolved to the half step and
+// returned as rotated primitives (rho, u_n, u_t1, u_t2, p, B_t1, B_t2).
+template <int D, class T>
+__device__ __forceinline__ void rotate7(const T (&w)[8], T (&q)[7]) {
+  q[0] = w[0];
+  q[1] = w[1 + D];
+  q[2] = w[1 + (D + 1) % 3];
+  q[3] = w[1 + (D + 2) % 3];
+  q[4] = w[4];
+  q[5] = w[5 + (D + 1) % 3];
+  q[6] = w[5 + (D + 2) % 3];
+}
+
+template <class T, int NDIM>
+struct Pred {
+  T m[3][7];  // low-side (minus) states per direction
+  T p[3][7];  // high-side (plus) states per direction
+};
+
+// Slopes, face states, Hancock increment and predicted states of one cell.
+// wx/wy/wz hold the neighbours (minus, plus) along each axis; fb[d][0/1] are
+// the cell's low/high face fields along d.
+template <class T, int NDIM>
+__device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8], const T (&wym)[8],
+                                        const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
+                                        const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
+                                        Pred<T, NDIM>& out) {
+  const T gm1 = gam - T(1);
+  const T gm1_inv = T(1) / gm1;
+  T sl[3][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    sl[0][q] = limiter_minmod(w[q] - wxm[q], wxp[q] - w[q]);
+    sl[1][q] = limiter_minmod(w[q] - wym[q], wyp[q] - w[q]);
+    if (NDIM == 3) sl[2][q] = limiter_minmod(w[q] - wzm[q], wzp[q] - w[q]);
+  }
+  T du[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) du[q] = T(0);
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+    T wl[8], wr[8], fl[8], fr[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      wl[q] = w[q] - T(0.5) * sl[d][q];
+      wr[q] = w[q] + T(0.5) * sl[d][q];
+    }
+    wl[5 + d] = fb[d][0];
+    wr[5 + d] = fb[d][1];
+    if (d == 0) {
+      flux_along<0>(wl, fl, gm1_inv);
+      flux_along<0>(wr, fr, gm1_inv);
+    } else if (d == 1) {
+      flux_along<1>(wl, fl, gm1_inv);
+      flux_along<1>(wr, fr, gm1_inv);
+    } else {
+      flux_along<2>(wl, fl, gm1_inv);
+      flux_along<2>(wr, fr, gm1_inv);
+    }
+    const T c = hdt * idx[d];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) du[q] -= c * (fr[q] - fl[q]);
+  }
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      T ws[8], us[8], wb[8];
+      const T h = side ? T(0.5) : T(-0.5);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ws[q] = w[q] + h * sl[d][q];
+      ws[5 + d] = fb[d][side];
+      to_conserved(ws, us, gm1_inv);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) us[q] += du[q];
+      to_primitive(us, wb, gm1);
+      ok = ok && (wb[0] > T(0)) && (wb[4] > T(0));
+      T(&dst)[7] = side ? out.p[d] : out.m[d];
+      if (d == 0) rotate7<0>(wb, dst);
+      else if (d == 1) rotate7<1>(wb, dst);
+      else rotate7<2>(wb, dst);
+    }
+  }
+  return ok;
+}
+
+template <class T>
+__device__ __forceinline__ void hlld7(const T (&l)[7], const T (&r)[7], T bn, T gam, T (&f)[7]) {
+  T ql[8] = {l[0], l[1], l[2], l[3], l[4], bn, l[5], l[6]};
+  T qr[8] = {r[0], r[1], r[2], r[3], r[4], bn, r[5], r[6]};
+  riemann_hlld(ql, qr, bn, gam, f);
+}
+
+constexpr int kW = 18;  // LDS plane edge: 16 thread columns + 1 ring cell each side
+
+// Ring entry r in [0, 68) of the 18x18 LDS plane -> (ex, ey).
+__device__ __forceinline__ void ring_entry(int r, int& ex, int& ey) {
+  if (r < 18) { ex = r; ey = 0; }
+  else if (r < 36) { ex = r - 18; ey = 17; }
+  else if (r < 52) { ex = 0; ey = r - 35; }
+  else { ex = 17; ey = r - 51; }
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
+                                              int nitems, DevState<T> U, DevFlux<T> F,
+                                              const double* __restrict__ dt0p, Phys ph, ErrBlock* err) {
+  __shared__ T sW[8][kW * kW];
+  __shared__ T sX[7][256];
+  __shared__ T sY[7][256];
+
+  const int tid = threadIdx.x;
+  const int tx = tid & 15;
+  const int ty = tid >> 4;
+  const T gam = T(ph.gamma);
+  const T gm1 = gam - T(1);
+
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const FluxItem item = items[it];
+    const GridDesc G = grids[item.grid];
+    const Idx<NDIM> ix(G);
+    const int gv = item.gv;
+    const int cl = -gv + 1;
+    const int chx = G.n[0] + gv - 1, chy = G.n[1] + gv - 1;
+    const int wlo = -gv, whix = G.n[0] + gv, whiy = G.n[1] + gv;  // valid input cells [wlo, whi)
+    const int x0 = item.x0, y0 = item.y0;
+    const int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
+    const bool act = cx >= cl && cx < chx && cy >= cl && cy < chy;
+    const bool own = act && tx >= 1 && ty >= 1;
+
+    // time step of this grid's level and 1/dx
+    double rl = 1.0;
+    for (int l = 0; l < G.level; ++l) rl *= (double)ph.ratio;
+    const T dt = T(dt0p[0] / rl);
+    const T hdt = T(0.5) * dt;
+    T idx[3];
+    idx[0] = T(rl / ph.dx0[0]);
+    idx[1] = T(rl / ph.dx0[1]);
+    idx[2] = T(NDIM == 3 ? rl / ph.dx0[2] : 0.0);
+
+    // own LDS entry and (for tid < 68) one ring entry
+    const int eo = (ty + 1) * kW + tx + 1;
+    int rex = 0, rey = 0;
+    if (tid < 68) ring_entry(tid, rex, rey);
+    const int rcx = x0 - 2 + rex, rcy = y0 - 2 + rey;
+    const bool rok = tid < 68 && rcx >= wlo && rcx < whix && rcy >= wlo && rcy < whiy;
+    const bool ook = cx >= wlo && cx < whix && cy >= wlo && cy < whiy;
+
+    const int kstart = NDIM == 3 ? max(item.z0 - 1, cl) : 0;
+    const int kend = NDIM == 3 ? item.z1 : 1;
+
+    T wprev[8], wcur[8], wnext[8], wring[8];
+    T zcarry[7];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) { wprev[q] = T(1); wcur[q] = T(1); wnext[q] = T(1); wring[q] = T(1); }
+#pragma unroll
+    for (int q = 0; q < 7; ++q) zcarry[q] = T(0);
+
+    // prologue: W(kstart-1) own (3D), W(kstart) own + ring into LDS
+    if (NDIM == 3 && ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart - 1), ix.sy, ix.sz, gm1, wprev);
+    if (ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart), ix.sy, ix.sz, gm1, wcur);
+    if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, kstart), ix.sy, ix.sz, gm1, wring);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      sW[q][eo] = wcur[q];
+      if (tid < 68) sW[q][rey * kW + rex] = wring[q];
+    }
+    __syncthreads();
+
+    for (int k = kstart; k < kend; ++k) {
+      if (NDIM == 3) {
+        if (ook) load_prim<T, NDIM>(U, ix(cx, cy, k + 1), ix.sy, ix.sz, gm1, wnext);
+        if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, k + 1), ix.sy, ix.sz, gm1, wring);
+      }
+      Pred<T, NDIM> pr;
+      if (act) {
+        T wxm[8], wxp[8], wym[8], wyp[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          wxm[q] = sW[q][eo - 1];
+          wxp[q] = sW[q][eo + 1];
+          wym[q] = sW[q][eo - kW];
+          wyp[q] = sW[q][eo + kW];
+        }
+        if ((wcur[0] <= T(0)) || (wcur[4] <= T(0))) flag_bad(err, ix(cx, cy, k));
+        const int64_t e = ix(cx, cy, k);
+        T fb[3][2];
+        fb[0][0] = U.f[5][e];
+        fb[0][1] = U.f[5][e + 1];
+        fb[1][0] = U.f[6][e];
+        fb[1][1] = U.f[6][e + ix.sy];
+        if (NDIM == 3) {
+          fb[2][0] = U.f[7][e];
+          fb[2][1] = U.f[7][e + ix.sz];
+        } else {
+          fb[2][0] = T(0);
+          fb[2][1] = T(0);
+        }
+        bool ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fb, hdt, idx, gam, pr);
+        if (!ok) flag_bad(err, e);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+          sX[q][tid] = pr.p[0][q];
+          sY[q][tid] = pr.p[1][q];
+        }
+      }
+      __syncthreads();
+      if (own && k >= item.z0) {
+        const int64_t e = ix(cx, cy, k);
+        T f[7];
+        if (cx > cl) {
+          T l[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) l[q] = sX[q][tid - 1];
+          hlld7(l, pr.m[0], U.f[5][e], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[0][q][e] = f[q];
+        }
+        if (cy > cl) {
+          T l[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - 16];
+          hlld7(l, pr.m[1], U.f[6][e], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
+        }
+        if (NDIM == 3 && k > cl) {
+          hlld7(zcarry, pr.m[2], U.f[7][e], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[2][q][e] = f[q];
+        }
+      }
+      if (NDIM == 3) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) zcarry[q] = pr.p[2][q];
+      }
+      __syncthreads();
+      if (NDIM == 3) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          sW[q][eo] = wnext[q];
+          if (tid < 68) sW[q][rey * kW + rex] = wring[q];
+          wprev[q] = wcur[q];
+          wcur[q] = wnext[q];
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Edge EMF along axis A at the edge whose high-side cell index is e:
+// mean of the two adjacent B-face fluxes of each of the other two directions
+// (E_A = -F_b(B_c) on b-faces, +F_c(B_b) on c-faces, b = A+1, c = A+2).
+template <int A, class T>
+__device__ __forceinline__ T edge_emf(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  T s1 = F.f[B][5][e - st[C]] + F.f[B][5][e];
+  T s2 = F.f[C][6][e - st[B]] + F.f[C][6][e];
+  return T(0.25) * (s2 - s1);
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
+                                                int nitems, DevState<T> Uin, DevState<T> Uout, DevFlux<T> F,
+                                                const double* __restrict__ dt0p, Phys ph) {
+  const int tx = threadIdx.x & 15;
+  const int ty = threadIdx.x >> 4;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const UpdItem item = items[it];
+    const GridDesc G = grids[item.grid];
+    const Idx<NDIM> ix(G);
+    const int gv = item.gv;
+    const int uhx = G.n[0] + gv - 2, uhy = G.n[1] + gv - 2, uhz = NDIM == 3 ? G.n[2] + gv - 2 : 0;
+    const int cx = item.x0 + tx, cy = item.y0 + ty;
+    if (cx > uhx || cy > uhy) continue;
+
+    double rl = 1.0;
+    for (int l = 0; l < G.level; ++l) rl *= (double)ph.ratio;
+    const T dt = T(dt0p[0] / rl);
+    T idx[3];
+    idx[0] = T(rl / ph.dx0[0]);
+    idx[1] = T(rl / ph.dx0[1]);
+    idx[2] = T(NDIM == 3 ? rl / ph.dx0[2] : 0.0);
+    const T cdx = dt * idx[0], cdy = dt * idx[1], cdz = dt * idx[2];
+    const int64_t st[3] = {1, ix.sy, NDIM == 3 ? ix.sz : 0};
+
+    for (int k = item.z0; k < item.z1; ++k) {
+      const int64_t e = ix(cx, cy, k);
+      const bool cell = cx < uhx && cy < uhy && (NDIM == 2 || k < uhz);
+      if (cell) {
+        // lab conserved slot -> rotated component of direction d
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+          T acc;
+          if (s == 0 || s == 4) {
+            acc = cdx * (F.f[0][s][e + 1] - F.f[0][s][e]) + cdy * (F.f[1][s][e + st[1]] - F.f[1][s][e]);
+            if (NDIM == 3) acc += cdz * (F.f[2][s][e + st[2]] - F.f[2][s][e]);
+          } else {
+            const int a = s - 1;
+            const int qx = 1 + (a + 3 - 0) % 3, qy = 1 + (a + 3 - 1) % 3, qz = 1 + (a + 3 - 2) % 3;
+            acc = cdx * (F.f[0][qx][e + 1] - F.f[0][qx][e]) + cdy * (F.f[1][qy][e + st[1]] - F.f[1][qy][e]);
+            if (NDIM == 3) acc += cdz * (F.f[2][qz][e + st[2]] - F.f[2][qz][e]);
+          }
+          Uout.f[s][e] = Uin.f[s][e] - acc;
+        }
+        if (NDIM == 2) {
+          // cell-centred Bz: x-flux component t2 (index 6), y-flux component t1 (index 5)
+          T acc = cdx * (F.f[0][6][e + 1] - F.f[0][6][e]) + cdy * (F.f[1][5][e + st[1]] - F.f[1][5][e]);
+          Uout.f[7][e] = Uin.f[7][e] - acc;
+        }
+      }
+      if (NDIM == 3) {
+        // faces: dB_d/dt = -(curl E)_d
+        if (cy < uhy && k < uhz) {  // Bx face (cx, cy, k)
+          T ez0 = edge_emf<2>(F, e, st), ez1 = edge_emf<2>(F, e + st[1], st);
+          T ey0 = edge_emf<1>(F, e, st), ey1 = edge_emf<1>(F, e + st[2], st);
+          Uout.f[5][e] = Uin.f[5][e] - (cdy * (ez1 - ez0) - cdz * (ey1 - ey0));
+        }
+        if (cx < uhx && k < uhz) {  // By face
+          T ex0 = edge_emf<0>(F, e, st), ex1 = edge_emf<0>(F, e + st[2], st);
+          T ez0 = edge_emf<2>(F, e, st), ez1 = edge_emf<2>(F, e + st[0], st);
+          Uout.f[6][e] = Uin.f[6][e] - (cdz * (ex1 - ex0) - cdx * (ez1 - ez0));
+        }
+        if (cx < uhx && cy < uhy) {  // Bz face
+          T ey0 = edge_emf<1>(F, e, st), ey1 = edge_emf<1>(F, e + st[0], st);
+          T ex0 = edge_emf<0>(F, e, st), ex1 = edge_emf<0>(F, e + st[1], st);
+          Uout.f[7][e] = Uin.f[7][e] - (cdx * (ey1 - ey0) - cdy * (ex1 - ex0));
+        }
+      } else {
+        // 2D: only E_z; edges are cell corners.  E_z = -F_x(By) on x-faces
+        // (x-flux t1 = y, index 5) and +F_y(Bx) on y-faces (y-flux t2 = x, index 6).
+        auto ez = [&](int64_t ee) {
+          T s1 = F.f[0][5][ee - st[1]] + F.f[0][5][ee];
+          T s2 = F.f[1][6][ee - st[0]] + F.f[1][6][ee];
+          return T(0.25) * (s2 - s1);
+        };
+        if (cy < uhy) {  // Bx face
+          T e0 = ez(e), e1 = ez(e + st[1]);
+          Uout.f[5][e] = Uin.f[5][e] - cdy * (e1 - e0);
+        }
+        if (cx < uhx) {  // By face
+          T e0 = ez(e), e1 = ez(e + st[0]);
+          Uout.f[6][e] = Uin.f[6][e] + cdx * (e1 - e0);
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <class T>
+void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> U, DevFlux<T> F,
+                 const double* dt0, Phys ph, ErrBlock* err, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (ndim == 3)
+    hipLaunchKernelGGL((k_flux<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, F, dt0, ph, err);
+  else
+    hipLaunchKernelGGL((k_flux<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, F, dt0, ph, err);
+}
+
+template <class T>
+void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> Uin,
+                   DevState<T> Uout, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (ndim == 3)
+    hipLaunchKernelGGL((k_update<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, Uin, Uout, F, dt0, ph);
+  else
+    hipLaunchKernelGGL((k_update<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, Uin, Uout, F, dt0, ph);
+}
+
+template void launch_flux<float>(int, const GridDesc*, const FluxItem*, int, DevState<float>, DevFlux<float>,
+                                 const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_flux<double>(int, const GridDesc*, const FluxItem*, int, DevState<double>, DevFlux<double>,
+                                  const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_update<float>(int, const GridDesc*, const UpdItem*, int, DevState<float>, DevState<float>,
+                                   DevFlux<float>, const double*, Phys, hipStream_t);
+template void launch_update<double>(int, const GridDesc*, const UpdItem*, int, DevState<double>, DevState<double>,
+                                    DevFlux<double>, const double*, Phys, hipStream_t);
+
+}  // namespace amr

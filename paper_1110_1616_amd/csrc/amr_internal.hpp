@@ -1,0 +1,81 @@
+// Internal types shared by the HIP kernels and the host runtime of
+// libamrmhd.so.  Not part of the public ABI (include/amr.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amr {
+
+// Device descriptor of one grid (patch).  The padded box holds every field:
+// P[d] = n[d] + 2g + 1 on active axes, 1 on inactive ones; element (i,j,k)
+// with i in [-g, n+g] sits at off + ((k+gz) P[1] + (j+g)) P[0] + (i+g).
+struct GridDesc {
+  int32_t n[3];
+  int32_t lo[3];
+  int32_t g;
+  int32_t level;
+  int32_t P[3];
+  int32_t pad;
+  int64_t off;
+};
+
+// Flux-kernel work item: one 15x15-cell column tile of one grid, owned
+// planes [z0, z1), advanced from valid band gv.  (x0, y0) is the first owned
+// cell of the tile.
+struct FluxItem {
+  int32_t grid;
+  int32_t gv;
+  int32_t x0, y0;
+  int32_t z0, z1;
+  int32_t pad0, pad1;
+};
+
+// Update-kernel work item: a 16x16-column tile of the update index box
+// starting at (x0, y0), planes [z0, z1).
+struct UpdItem {
+  int32_t grid;
+  int32_t gv;
+  int32_t x0, y0;
+  int32_t z0, z1;
+  int32_t pad0, pad1;
+};
+
+// Physics constants passed by value.
+struct Phys {
+  double gamma;
+  double dx0[3];
+  int32_t ndim;
+  int32_t ratio;
+};
+
+template <class T> struct DevState {
+  T* f[8];
+};
+
+// Face fluxes of one substep: F[d][q], rotated components
+// (rho, m_n, m_t1, m_t2, E, B_t1, B_t2) of direction d, stored at the
+// element of the face's high-side cell (face index f along d <-> cell f).
+template <class T> struct DevFlux {
+  T* f[3][7];
+};
+
+// Error flag block in device memory: word 0 = flags, word 1..2 = first bad
+// element (int64), words 4.. = reduction scratch.
+struct ErrBlock {
+  uint32_t flags;
+  uint32_t pad;
+  int64_t first_bad;
+};
+
+constexpr int kFluxTile = 15;  // owned cells per tile edge of the flux kernel
+constexpr int kUpdTile = 16;   // cells per tile edge of the update kernel
+
+// Host-side launchers (defined in the .hip translation units).
+template <class T>
+void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> U, DevFlux<T> F,
+                 const double* dt0, Phys ph, ErrBlock* err, hipStream_t s);
+template <class T>
+void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> Uin,
+                   DevState<T> Uout, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s);
+
+}  // namespace amr

@@ -1,0 +1,72 @@
+"""CPU checks of the C ABI library: it loads without a GPU, exports every
+function include/amr.h declares, and rejects bad hierarchies synchronously
+(amr_create validates on the host before touching the device)."""
+
+import ctypes as C
+
+import pytest
+
+from paper_1110_1616_amd import amr as A
+
+
+def test_library_exports_every_header_function():
+    L = A.lib()
+    names = A.header_functions()
+    assert "amr_advance_patches" in names and "amr_fill_ghosts_prolong" in names
+    assert "amr_restrict_fluxfix" in names and "amr_advance_adjoint" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _params(**kw):
+    p = A.amr_params()
+    p.ndim, p.nlevels, p.ratio, p.ghost, p.dtype = 3, 1, 2, 4, A.AMR_F64
+    for d in range(3):
+        p.bc[d] = 0
+        p.domain[d] = 16
+        p.dx0[d] = 1.0 / 16
+    p.gamma, p.cfl = 5.0 / 3.0, 0.4
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _grid(level, lo, hi):
+    return A.amr_grid(level, (C.c_int32 * 3)(*lo), (C.c_int32 * 3)(*hi))
+
+
+@pytest.mark.parametrize("kw,grids,msg", [
+    (dict(ndim=4), [((0, 0, 0), (16, 16, 16))], "ndim"),
+    (dict(ghost=1), [((0, 0, 0), (16, 16, 16))], "ghost"),
+    (dict(nlevels=2, ghost=3), [((0, 0, 0), (16, 16, 16))], "ghost"),
+    (dict(gamma=1.0), [((0, 0, 0), (16, 16, 16))], "gamma"),
+    ({}, [((0, 0, 0), (17, 16, 16))], "outside"),
+    ({}, [((0, 0, 0), (8, 16, 16)), ((4, 0, 0), (16, 16, 16))], "overlap"),
+])
+def test_create_rejects_bad_input(kw, grids, msg):
+    p = _params(**kw)
+    gl = [_grid(0, lo, hi) for lo, hi in grids]
+    arr = (A.amr_grid * len(gl))(*gl)
+    h = C.c_void_p()
+    rc = A.lib().amr_create(C.byref(p), arr, len(gl), C.byref(h))
+    assert rc == A.AMR_EINVAL
+    assert h.value is None
+    assert msg in A.lib().amr_last_error().decode()
+
+
+def test_create_rejects_misaligned_and_unnested_fine_grids():
+    p = _params(nlevels=2)
+    cases = [
+        [_grid(0, (0, 0, 0), (16, 16, 16)), _grid(1, (3, 4, 4), (12, 12, 12))],  # not aligned to R
+        [_grid(0, (0, 0, 0), (8, 16, 16)), _grid(0, (8, 0, 0), (16, 16, 16)), _grid(1, (0, 0, 0), (8, 8, 8)),
+         _grid(1, (2, 2, 2), (6, 6, 6))],  # fine overlap
+    ]
+    for gl in cases:
+        arr = (A.amr_grid * len(gl))(*gl)
+        h = C.c_void_p()
+        assert A.lib().amr_create(C.byref(p), arr, len(gl), C.byref(h)) == A.AMR_EINVAL
+
+
+def test_strerror_names_every_status():
+    for s in (0, -1, -2, -3, -4, -5):
+        assert A.lib().amr_strerror(s).decode() != "unknown status"
