@@ -137,21 +137,23 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids, const int4* __restrict__ items,
                                              int nitems, DevState<T> U, Phys ph, unsigned long long* acc,
                                              ErrBlock* err) {
   __shared__ double red[4];
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int2 item = items[it];
+    // item: (grid, plane k, first row j0, rows)
+    const int4 item = items[it];
     const GridDesc G = grids[item.x];
     const int k = item.y;
     const int64_t sy = G.P[0], sz = (int64_t)G.P[0] * G.P[1];
-    const int64_t base = G.off + G.g + G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0) + (int64_t)k * sz;
-    const int nxy = G.n[0] * G.n[1];
+    const int64_t base = G.off + G.g + G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0) + (int64_t)k * sz +
+                         (int64_t)item.z * sy;
+    const int ncell = G.n[0] * item.w;
     double m = 0.0;
-    for (int c = threadIdx.x; c < nxy; c += blockDim.x) {
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
       const int i = c % G.n[0], j = c / G.n[0];
       const int64_t e = base + i + j * sy;
       T u[8], w[8];
@@ -304,7 +306,7 @@ void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const Prolo
 }
 
 template <class T>
-void launch_cfl(int ndim, const GridDesc* grids, const int2* items, int nitems, DevState<T> U, Phys ph,
+void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> U, Phys ph,
                 unsigned long long* acc, ErrBlock* err, double cfl, double* dt0, hipStream_t s) {
   if (nitems > 0) {
     if (ndim == 3)
@@ -342,7 +344,7 @@ void launch_store(int ndim, const GridDesc& G, DevState<T> U, double* const* out
   template void launch_copy<T>(int, const CopyEntry*, int, int4, DevState<T>, hipStream_t);                       \
   template void launch_prolong<T>(int, const ProlongEntry*, int, const ProlongEntry*, int, const GridDesc*,       \
                                   DevState<T>, Phys, hipStream_t);                                                \
-  template void launch_cfl<T>(int, const GridDesc*, const int2*, int, DevState<T>, Phys, unsigned long long*,     \
+  template void launch_cfl<T>(int, const GridDesc*, const int4*, int, DevState<T>, Phys, unsigned long long*,     \
                               ErrBlock*, double, double*, hipStream_t);                                           \
   template void launch_load_prim<T>(int, const GridDesc&, const double* const*, const double* const*,            \
                                     DevState<T>, double, hipStream_t);                                            \

@@ -27,7 +27,7 @@ template <class T>
 void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const ProlongEntry* faces, int nfaces,
                     const GridDesc* grids, DevState<T> U, Phys ph, hipStream_t s);
 template <class T>
-void launch_cfl(int ndim, const GridDesc* grids, const int2* items, int nitems, DevState<T> U, Phys ph,
+void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> U, Phys ph,
                 unsigned long long* acc, ErrBlock* err, double cfl, double* dt0, hipStream_t s);
 template <class T>
 void launch_load_prim(int ndim, const GridDesc& G, const double* const* prim, const double* const* b,

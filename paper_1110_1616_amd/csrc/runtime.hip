@@ -82,7 +82,7 @@ struct amr_hierarchy {
   UpdItem* d_uitems = nullptr;
   std::vector<FluxItem> h_fitems;
   std::vector<UpdItem> h_uitems;
-  int2* d_cfl = nullptr;
+  int4* d_cfl = nullptr;
   int n_cfl = 0;
   ErrBlock* d_err = nullptr;  // error block + CFL accumulator (handle-owned)
 
@@ -314,11 +314,14 @@ void build_lists(amr_hierarchy* h) {
     }
   h->d_fitems = dev_upload(h->h_fitems);
   h->d_uitems = dev_upload(h->h_uitems);
-  // CFL items: one per (grid, interior plane)
-  std::vector<int2> cf;
+  // CFL items: (grid, interior plane, first row, rows), about 1k cells each
+  std::vector<int4> cf;
   for (int gi = 0; gi < (int)h->grids.size(); ++gi) {
-    const int nz = h->ndim == 3 ? h->desc[gi].n[2] : 1;
-    for (int k = 0; k < nz; ++k) cf.push_back(make_int2(gi, k));
+    const GridDesc& G = h->desc[gi];
+    const int nz = h->ndim == 3 ? G.n[2] : 1;
+    const int rows = std::max(1, std::min(G.n[1], 1024 / std::max(1, G.n[0])));
+    for (int k = 0; k < nz; ++k)
+      for (int j0 = 0; j0 < G.n[1]; j0 += rows) cf.push_back(make_int4(gi, k, j0, std::min(rows, G.n[1] - j0)));
   }
   h->n_cfl = (int)cf.size();
   h->d_cfl = dev_upload(cf);
