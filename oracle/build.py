@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["oracle_capi.cpp"]
+SOURCES = ["oracle_capi.cpp", "amr_oracle.cpp"]
 HEADERS = ["scheme.hpp"]
 
 

@@ -214,3 +214,91 @@ def conserved_interior(ic, gamma):
     (zero steps of a uniform run)."""
     f, _ = uniform_run(ic, gamma, 0.4, 0, g=2)
     return f
+
+
+# ------------------------------------------------------------ hierarchies
+def _grid_desc(ndim, grids):
+    rows = []
+    for (l, lo, hi) in grids:
+        lo3 = list(lo) + [0] * (3 - len(lo))
+        hi3 = list(hi) + [1] * (3 - len(hi))
+        rows.append([l] + lo3 + hi3)
+    return np.ascontiguousarray(np.array(rows, dtype=np.int32))
+
+
+def _gshape(ndim, lo, hi):
+    n = [hi[a] - lo[a] for a in range(ndim)]
+    return tuple(n)
+
+
+def amr_run(ndim, N0, nlev, g, grids, fields, ncoarse, gamma=5.0 / 3.0, cfl=0.4, dts=None):
+    """Run ncoarse coarse steps of a hierarchy in the serial level order
+    (level cycle 0, 1, 2, 2, 1, 2, 2 for three levels).  fields: per grid
+    dict(prim=[5 arrays], b=[3 arrays]).  Returns (per-grid 8 arrays, dts)."""
+    L = lib()
+    L.orc_amr_last_error.restype = C.c_char_p
+    desc = _grid_desc(ndim, grids)
+    prim = [a for f in fields for a in f["prim"]]
+    bb = [a for f in fields for a in f["b"]]
+    k1, pp = _ptrs(prim)
+    k2, pb = _ptrs(bb)
+    outs = []
+    for (l, lo, hi) in grids:
+        outs.append([np.zeros(s) for s in interior_shapes(ndim, _gshape(ndim, lo, hi))])
+    k3, po = _ptrs([a for o in outs for a in o])
+    dts_out = np.zeros(max(ncoarse, 1))
+    pin = None
+    if dts is not None:
+        dts_in = np.ascontiguousarray(dts, dtype=np.float64)
+        pin = dts_in.ctypes.data_as(_dp)
+    dx0 = [1.0 / N0[a] for a in range(ndim)]
+    rc = L.orc_amr_run(C.c_int(ndim), _ivec(N0), C.c_int(nlev), C.c_int(g), C.c_double(gamma), C.c_double(cfl),
+                       _dvec(dx0), C.c_int(len(grids)), desc.ctypes.data_as(_ip), pp, pb, C.c_int(ncoarse), pin, po,
+                       dts_out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise RuntimeError("oracle amr_run: " + L.orc_amr_last_error().decode())
+    res = [k3[8 * i:8 * i + 8] for i in range(len(grids))]
+    return res, dts_out[:ncoarse]
+
+
+def amr_time(ndim, N0, nlev, g, grids, fields, ncoarse, gamma=5.0 / 3.0, cfl=0.4, threads=None):
+    L = lib()
+    L.orc_amr_time.restype = C.c_double
+    L.orc_amr_last_error.restype = C.c_char_p
+    if threads:
+        L.orc_set_threads(int(threads))
+    desc = _grid_desc(ndim, grids)
+    k1, pp = _ptrs([a for f in fields for a in f["prim"]])
+    k2, pb = _ptrs([a for f in fields for a in f["b"]])
+    dx0 = [1.0 / N0[a] for a in range(ndim)]
+    t = L.orc_amr_time(C.c_int(ndim), _ivec(N0), C.c_int(nlev), C.c_int(g), C.c_double(gamma), C.c_double(cfl),
+                       _dvec(dx0), C.c_int(len(grids)), desc.ctypes.data_as(_ip), pp, pb, C.c_int(ncoarse))
+    if t < 0:
+        raise RuntimeError("oracle amr_time: " + L.orc_amr_last_error().decode())
+    return t
+
+
+def amr_fill(ndim, N0, nlev, g, grids, cons, level, full):
+    """Fill the band of every grid of `level` from given conserved interiors
+    (per grid 8 interior-layout arrays).  Returns per-grid banded arrays."""
+    L = lib()
+    L.orc_amr_last_error.restype = C.c_char_p
+    desc = _grid_desc(ndim, grids)
+    k1, pc = _ptrs([a for c in cons for a in c])
+    outs = []
+    for (l, lo, hi) in grids:
+        outs.append([np.zeros(s) for s in banded_shapes(ndim, _gshape(ndim, lo, hi), g)])
+    k2, po = _ptrs([a for o in outs for a in o])
+    dx0 = [1.0 / N0[a] for a in range(ndim)]
+    rc = L.orc_amr_fill(C.c_int(ndim), _ivec(N0), C.c_int(nlev), C.c_int(g), _dvec(dx0), C.c_int(len(grids)),
+                        desc.ctypes.data_as(_ip), pc, C.c_int(level), C.c_int(1 if full else 0), po)
+    if rc != 0:
+        raise RuntimeError("oracle amr_fill: " + L.orc_amr_last_error().decode())
+    return [k2[8 * i:8 * i + 8] for i in range(len(grids))]
+
+
+def amr_level_order(nlev):
+    """Levels in the order the serial cycle advances them in one coarse step."""
+    buf = (C.c_int * 4096)()
+    n = lib().orc_amr_level_order(C.c_int(nlev), buf, 4096)
+    return list(buf[:n])

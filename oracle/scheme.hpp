@@ -344,6 +344,22 @@ struct NonPhysical : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
 
+// Face fluxes (lab-frame slots, stored at the high-side cell of each face,
+// one array per direction) and edge EMFs (one array per edge axis, stored at
+// the high-side cell in the two other axes) of one step, for the
+// synchronisation of AMR levels.  Same cell indexing as the patch.
+template <class T> struct StepCapture {
+  std::vector<T> flux;  // [d][cell][slot]
+  std::vector<T> emf;   // [a][cell]
+  size_t ncell = 0;
+  int ex[3] = {1, 1, 1}, g[3] = {0, 0, 0};
+  size_t cid(int i, int j, int k) const {
+    return ((size_t)(k + g[2]) * ex[1] + (size_t)(j + g[1])) * ex[0] + (size_t)(i + g[0]);
+  }
+  const T& F(int d, int slot, int i, int j, int k) const { return flux[((size_t)d * ncell + cid(i, j, k)) * NVAR + slot]; }
+  const T& E(int a, int i, int j, int k) const { return emf[(size_t)a * ncell + cid(i, j, k)]; }
+};
+
 // ---------------------------------------------------------------- one step
 // One unsplit MUSCL-Hancock / HLLD / CT step on a patch whose input is valid
 // on cells [-gv, n+gv) and faces [-gv, n+gv].  Output is written on cells
@@ -358,7 +374,7 @@ struct NonPhysical : std::runtime_error {
 //   of the four adjacent face values, (7) conservative update of cells and CT
 //   update of faces.
 template <class T>
-void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P) {
+void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P, StepCapture<T>* cap = nullptr) {
   const Layout& L = in.L;
   const int nd = L.ndim;
   const double gamma = P.gamma;
@@ -564,6 +580,15 @@ void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P) 
           }
           out.at(5 + d, i, j, k) = in.at(5 + d, i, j, k) - dt * curl;
         }
+  }
+  if (cap) {
+    cap->flux = std::move(Flux);
+    cap->emf = std::move(Emf);
+    cap->ncell = ncell;
+    for (int a = 0; a < 3; ++a) {
+      cap->ex[a] = ex[a];
+      cap->g[a] = L.gd(a);
+    }
   }
 }
 

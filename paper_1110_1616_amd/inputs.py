@@ -268,3 +268,192 @@ def advected_profile(N, seed=7, v=(0.37, 0.0, 0.0), p=1.0, B=(0.0, 0.0, 0.0), nd
     u["prim"][0] = rho
     u["dx"] = [1.0 / nx, 1.0 / nx, 1.0 / nx if ndim == 3 else 1.0]
     return u
+
+
+# ---------------------------------------------------------------- hierarchies
+def _partition(rng, length, lo_ext, hi_ext):
+    """Split `length` cells into consecutive even segments with extents in
+    [lo_ext, hi_ext] (seeded); the last segment absorbs the remainder."""
+    segs = []
+    left = length
+    while left > 0:
+        if left <= hi_ext:
+            if left >= lo_ext or not segs:
+                segs.append(left)
+            else:
+                segs[-1] += left
+                if segs[-1] > hi_ext:  # split the last two evenly
+                    t = segs.pop()
+                    a = (t // 2) // 2 * 2
+                    segs += [a, t - a]
+            break
+        e = int(rng.integers(lo_ext // 2, hi_ext // 2 + 1)) * 2
+        if left - e < lo_ext and left - e != 0:
+            e = left - lo_ext if left - lo_ext <= hi_ext else e
+        segs.append(e)
+        left -= e
+    return segs
+
+
+def _tile_box(rng, lo, hi, ndim, lo_ext, hi_ext):
+    axes = []
+    for a in range(ndim):
+        segs = _partition(rng, hi[a] - lo[a], lo_ext, hi_ext)
+        starts = np.cumsum([0] + segs[:-1]) + lo[a]
+        axes.append(list(zip(starts, segs)))
+    boxes = []
+    if ndim == 2:
+        for (y0, ny) in axes[1]:
+            for (x0, nx) in axes[0]:
+                boxes.append(((int(x0), int(y0)), (int(x0 + nx), int(y0 + ny))))
+    else:
+        for (z0, nz) in axes[2]:
+            for (y0, ny) in axes[1]:
+                for (x0, nx) in axes[0]:
+                    boxes.append(((int(x0), int(y0), int(z0)), (int(x0 + nx), int(y0 + ny), int(z0 + nz))))
+    return boxes
+
+
+def amr_hierarchy(ndim, N0, nlevels, seed, ext=(8, 32), fill_fraction=0.125, ghost=4, max_boxes=4, ratio=2):
+    """Seeded nested hierarchy.  Level 0 tiles the periodic domain; each
+    level l >= 1 covers about `fill_fraction` of the volume of level l-1 with
+    1..max_boxes boxes placed inside the level-(l-1) boxes shrunk by the
+    nesting buffer (ghost/R + 1 coarse cells); every box is tiled by grids
+    whose extents are even and drawn from [ext[0], ext[1]].  Returns a list of
+    (level, lo, hi) in level-l cell indices."""
+    rng = np.random.default_rng(seed)
+    N0 = tuple(int(v) for v in N0)[:ndim]
+    grids = [(0, lo, hi) for lo, hi in _tile_box(rng, (0,) * ndim, N0, ndim, ext[0], ext[1])]
+    parents = [((0,) * ndim, N0)]  # boxes of the previous level (level units)
+    buf = ghost // ratio + 1
+    for l in range(1, nlevels):
+        cover = sum(np.prod([h - lo for lo, h in zip(b[0], b[1])]) for b in parents)
+        target = fill_fraction * cover * ratio ** ndim  # cells on level l
+        nb = int(rng.integers(1, max_boxes + 1))
+        boxes = []
+        tries = 0
+        while len(boxes) < nb and tries < 1000:
+            tries += 1
+            vol = target / nb
+            side = max(ext[0], int(round(vol ** (1.0 / ndim) / 2)) * 2)
+            pb = parents[int(rng.integers(0, len(parents)))]
+            # parent box in level-l units, shrunk by the buffer (periodic
+            # level 0 needs no shrink across the domain edge)
+            lo_p = [pb[0][a] * ratio + (buf * ratio if l > 1 else 0) for a in range(ndim)]
+            hi_p = [pb[1][a] * ratio - (buf * ratio if l > 1 else 0) for a in range(ndim)]
+            ext_ok = all(hi_p[a] - lo_p[a] >= side for a in range(ndim))
+            if not ext_ok:
+                side = min(hi_p[a] - lo_p[a] for a in range(ndim)) // 2 * 2
+                if side < ext[0]:
+                    continue
+            lo = []
+            for a in range(ndim):
+                span = (hi_p[a] - lo_p[a] - side) // 2
+                lo.append(lo_p[a] + 2 * int(rng.integers(0, span + 1)))
+            hi = [x + side for x in lo]
+            # keep boxes apart by the nesting buffer of the next level
+            ok = True
+            for (blo, bhi) in boxes:
+                if all(lo[a] < bhi[a] + 2 * buf and blo[a] < hi[a] + 2 * buf for a in range(ndim)):
+                    ok = False
+            if ok:
+                boxes.append((tuple(lo), tuple(hi)))
+        for (blo, bhi) in boxes:
+            grids += [(l, lo, hi) for lo, hi in _tile_box(rng, blo, bhi, ndim, ext[0], ext[1])]
+        parents = boxes
+    return grids
+
+
+def _edge_mean_factor(k, h_fine, r):
+    """Mean of cos(theta0 + m * 2 pi k h_fine) over m = 0..r-1 about the
+    centre of the run: cos(theta_mid) * sin(r d/2) / (r sin(d/2))."""
+    d = TWO_PI * k * h_fine
+    if r == 1 or abs(np.sin(d / 2)) < 1e-300:
+        return 1.0
+    return np.sin(r * d / 2) / (r * np.sin(d / 2))
+
+
+def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1, ratio=2):
+    """Per-grid primitive data of a hierarchy, sampled from one set of smooth
+    random fields.  Cells take point values at their centres.  The vector
+    potential of every level is the mean of the finest level's edge samples
+    along each edge (a closed form per Fourier mode), so face B of every
+    level is the discrete curl of consistent potentials: a coarse face equals
+    the mean of the finest faces on it, up to rounding.  Amplitudes are set
+    from level 0.  Returns a list of dict(prim=[...], b=[...]) per grid."""
+    rng = np.random.default_rng(seed)
+    fld = _Field(rng, ndim)
+    N0 = tuple(int(v) for v in N0)[:ndim]
+    Lf = nlevels - 1
+
+    def level_pot(l):
+        r = ratio ** (Lf - l)
+        hf = [1.0 / (N0[a] * ratio ** Lf) for a in range(ndim)] + [1.0] * (3 - ndim)
+
+        def pot(comp, x, y, z):
+            out = np.zeros_like(x)
+            for m in range(8):
+                fac = 1.0
+                if comp < ndim:  # averaged along the edge direction
+                    fac = _edge_mean_factor(fld.k_a[m][comp], hf[comp], r)
+                out += fld.a_a[m, comp] * fac * np.cos(_phase(fld.k_a[m], fld.phi_a[m], x, y, z))
+            return out
+
+        return pot
+
+    def sample_grid(l, lo, hi):
+        n = [hi[a] - lo[a] for a in range(ndim)]
+        Nl = [N0[a] * ratio ** l for a in range(ndim)]
+        h = [1.0 / Nl[a] for a in range(ndim)]
+        xs = (np.arange(lo[0], hi[0]) + 0.5) * h[0]
+        ys = (np.arange(lo[1], hi[1]) + 0.5) * h[1]
+        zs = (np.arange(lo[2], hi[2]) + 0.5) * h[2] if ndim == 3 else np.zeros(1)
+        x, y, z = _grid(xs, ys, zs)
+        rho = 1.0 + rho_amp * fld.f_rho(x, y, z)
+        v = fld.curl_psi(x, y, z)
+        pot = level_pot(l)
+
+        def wp(a, count, off):
+            return (np.arange(lo[a], lo[a] + count) % Nl[a] + off) * h[a]
+
+        nx, ny = n[0], n[1]
+        if ndim == 3:
+            nz = n[2]
+            x_, y_, z_ = _grid(wp(0, nx, 0.5), wp(1, ny + 1, 0.0), wp(2, nz + 1, 0.0))
+            ax = pot(0, x_, y_, z_)
+            x_, y_, z_ = _grid(wp(0, nx + 1, 0.0), wp(1, ny, 0.5), wp(2, nz + 1, 0.0))
+            ay = pot(1, x_, y_, z_)
+            x_, y_, z_ = _grid(wp(0, nx + 1, 0.0), wp(1, ny + 1, 0.0), wp(2, nz, 0.5))
+            az = pot(2, x_, y_, z_)
+            bx = (az[:, 1:, :] - az[:, :-1, :]) / h[1] - (ay[1:, :, :] - ay[:-1, :, :]) / h[2]
+            by = (ax[1:, :, :] - ax[:-1, :, :]) / h[2] - (az[:, :, 1:] - az[:, :, :-1]) / h[0]
+            bz = (ay[:, :, 1:] - ay[:, :, :-1]) / h[0] - (ax[:, 1:, :] - ax[:, :-1, :]) / h[1]
+        else:
+            zero = np.zeros(1)
+            x_, y_, z_ = _grid(wp(0, nx + 1, 0.0), wp(1, ny + 1, 0.0), zero)
+            az = pot(2, x_, y_, z_)[0]
+            x_, y_, z_ = _grid(wp(0, nx, 0.5), wp(1, ny + 1, 0.0), zero)
+            ax = pot(0, x_, y_, z_)[0]
+            x_, y_, z_ = _grid(wp(0, nx + 1, 0.0), wp(1, ny, 0.5), zero)
+            ay = pot(1, x_, y_, z_)[0]
+            bx = ((az[1:, :] - az[:-1, :]) / h[1])[None]
+            by = (-(az[:, 1:] - az[:, :-1]) / h[0])[None]
+            bz = ((ay[:, 1:] - ay[:, :-1]) / h[0] - (ax[1:, :] - ax[:-1, :]) / h[1])[None]
+        return rho, v, [bx, by, bz]
+
+    raw = [sample_grid(l, lo, hi) for (l, lo, hi) in grids]
+    # amplitudes from level 0 (which tiles the domain)
+    vs, bs, nc = 0.0, 0.0, 0
+    for (l, lo, hi), (rho, v, b) in zip(grids, raw):
+        if l != 0:
+            continue
+        vs += float(np.sum(v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
+        nc += rho.size
+        bs += _face_mean_sq(ndim, b) * rho.size
+    vscale = v_rms / np.sqrt(vs / nc)
+    bscale = b_rms / np.sqrt(bs / nc)
+    out = []
+    for (l, lo, hi), (rho, v, b) in zip(grids, raw):
+        prim = [rho, v[0] * vscale, v[1] * vscale, v[2] * vscale, np.ones_like(rho)]
+        out.append({"prim": prim, "b": [c * bscale for c in b]})
+    return out
