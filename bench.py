@@ -73,7 +73,7 @@ def single_grid_workload(args):
         s = state["s"]
         band = 4 if s % 2 == 0 else 2
         if band == 4:
-            H.fill(0, A.AMR_FILL_FULL, state["U"])
+            H.fill(0, A.AMR_FILL_SAME_LEVEL, state["U"])
         H.compute_dt(state["U"])
         H.advance(state["U"], state["V"], cycle=0, band=band)
         state["U"], state["V"] = state["V"], state["U"]

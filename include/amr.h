@@ -102,6 +102,13 @@ typedef struct amr_hierarchy amr_hierarchy;
  * why (amr_last_error() has the text). */
 amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids, amr_hierarchy** out);
 
+/* Run every check and table build of amr_create() on the host only (no
+ * device is touched; usable without a GPU).  stats (may be NULL, else 8
+ * entries) receives: grids, elements per state pool, workspace bytes, copy
+ * map entries, prolongation entries, synchronisation entries, flux work
+ * items, update work items. */
+amr_status amr_validate(const amr_params* p, const amr_grid* grids, int32_t ngrids, int64_t* stats);
+
 /* Release the handle and its device tables (synchronises the device). */
 amr_status amr_destroy(amr_hierarchy* h);
 
@@ -126,51 +133,88 @@ amr_status amr_load_primitive(amr_hierarchy* h, int32_t grid, const double* cons
 amr_status amr_store_interior(amr_hierarchy* h, int32_t grid, const amr_state* U, double* const* out,
                               void* stream);
 
+/* Two-buffer states.  Every level is double buffered: a hierarchy state is
+ * a pair (U_a, U_b) plus a parity word whose bit l says that level l's
+ * current data is in U_b (else in U_a).  An advance of level l reads its
+ * current buffer and writes the other one, then the caller (or
+ * amr_coarse_step) flips bit l.  A single-level caller may keep parity 0 and
+ * swap U_a / U_b itself. */
+
 /* Time step of the coarse level: dt0 = C / max over all interior cells of
- * all levels of sum_d (|v_d| + c_f,d) / dx0_d, c_f,d the fast speed along d.
- * Written to the device scalar *dt0 (no host synchronisation); level l then
- * steps dt0 / R^l.  The maximum is a wavefront reduction plus an
- * order-independent atomic maximum, so dt0 is deterministic.  workspace:
- * the advance workspace (its first 256 bytes hold the reduction scratch). */
-amr_status amr_compute_dt(amr_hierarchy* h, const amr_state* U, double* dt0, void* workspace, void* stream);
+ * all levels of sum_d (|v_d| + c_f,d) / dx0_d, c_f,d the fast speed along d
+ * of the cell-centred state.  Written to the device scalar *dt0 (no host
+ * synchronisation); level l then steps dt0 / R^l.  The maximum is a
+ * wavefront reduction plus an order-independent atomic maximum on the bit
+ * pattern of the non-negative value, so dt0 is deterministic. */
+amr_status amr_compute_dt(amr_hierarchy* h, const amr_state* U_a, const amr_state* U_b, uint32_t parity,
+                          double* dt0, void* stream);
 
-/* Ghost fill of every grid of `level` in U (paper: (P)rolongation plus the
- * same-level exchange that ghost cells need; Sec. 4).  Band elements that
+/* Ghost fill of every grid of `level` (the paper's (P)rolongation plus the
+ * same-level exchange that ghost cells need; Sec. 4).  U_level holds the
+ * level's current data and receives the band; U_parent holds level-1's
+ * current data (may be NULL for level 0 or SAME_LEVEL).  Band elements that
  * lie in (cells) or on the boundary of (faces) another grid's interior of the
- * same level, periodic images included, are copied from it.  With
- * AMR_FILL_FULL the remaining band elements are prolonged from level-1 data
- * in the same U: cells by minmod-limited linear reconstruction of the
- * conserved variables, faces by the divergence-free reconstruction of
- * Balsara (2001, J. Comput. Phys. 174, 614); at level 0 they take the
- * outflow boundary (zero gradient; normal face copied from the last domain
- * face).  AMR_FILL_SAME_LEVEL copies only (the refresh before substeps k >=
- * 1 of a parent step). */
-amr_status amr_fill_ghosts_prolong(amr_hierarchy* h, int32_t level, int32_t mode, amr_state* U, void* stream);
+ * same level, periodic images included, are copied from the lowest-id such
+ * grid.  With AMR_FILL_FULL the remaining band elements of a level > 0 are
+ * prolonged from the parent level: cells by minmod-limited linear
+ * reconstruction of the conserved variables, faces by the divergence-free
+ * reconstruction of Balsara (2001, J. Comput. Phys. 174, 614), R = 2.  At
+ * level 0 band elements outside a non-periodic boundary copy the nearest
+ * domain element (outflow).  AMR_FILL_SAME_LEVEL copies only: the refresh
+ * before substeps k >= 1 of a parent step. */
+amr_status amr_fill_ghosts_prolong(amr_hierarchy* h, int32_t level, int32_t mode, amr_state* U_level,
+                                   const amr_state* U_parent, void* stream);
 
-/* One substep of a set of grids from U_in to U_out (the (A)dvance of Sec. 4).
- * Each grid g advances by dt0 / R^level(g) on the region its valid band
- * allows: input valid on band `band` (cells [-band, n+band)), output valid on
- * band-2.  cycle >= 0 selects the prebuilt batched work list of launch cycle
- * `cycle` (0 <= cycle < R^(nlevels-1)): every grid of every level whose step
- * falls in that cycle, in one batched launch ordered finest level first, with
- * each level's band taken from its substep index (band argument ignored).
- * cycle < 0 advances exactly the grids in grid_subset[0..nsubset) (host
- * array) with the given band, one grid per launch, in list order: the
- * per-grid path.  Boundary fluxes and EMFs of each stepped grid are
- * accumulated into the synchronisation registers in workspace. */
+/* One substep of a set of grids (the (A)dvance of Sec. 4): each grid of level
+ * l reads its level's current buffer (parity bit l), advances by dt0 / R^l
+ * and writes the other buffer; the caller flips the bits afterwards.  Input
+ * is valid on the grid's band `band` (cells [-band, n+band)); output is valid
+ * on band-2 (two cells per step feed the slopes and the edge EMFs).
+ *   cycle >= 0, band <= 0: the prebuilt batched list of launch cycle
+ *     `cycle` (0 <= cycle < R^(nlevels-1)): every grid of every level whose
+ *     step falls in that cycle, finest level first, larger grids first, in
+ *     one flux and one update launch; level l steps in cycle c when c is a
+ *     multiple of R^(nlevels-1-l), its band is g at the first substep of a
+ *     parent step and g-2 at the second.
+ *   cycle >= 0, band > 0: single-level hierarchies only: all grids, that band.
+ *   cycle < 0: exactly the grids grid_subset[0..nsubset) (host array), each
+ *     in its own launches, in list order, with the given band: the per-grid
+ *     path.
+ * Afterwards the coarse/fine registers of the levels that stepped are
+ * written into workspace (coarse side for level l < nlevels-1, fine side,
+ * slot of the substep, for l > 0); they are valid once every grid of the
+ * level has stepped. */
 amr_status amr_advance_patches(amr_hierarchy* h, int32_t cycle, const int32_t* grid_subset, int32_t nsubset,
-                               int32_t band, const amr_state* U_in, amr_state* U_out, const double* dt0,
-                               void* workspace, void* stream);
+                               int32_t band, const amr_state* U_a, const amr_state* U_b, uint32_t parity,
+                               const double* dt0, void* workspace, void* stream);
 
 /* Synchronise level fine_level-1 with fine_level after the fine level's R
- * substeps (the (S)ynchronise and (R)estrict of Sec. 4): reflux of the
- * uncovered coarse cells at coarse/fine faces with the time-integrated fine
- * fluxes, correction of uncovered coarse faces at coarse/fine edges with the
- * time-integrated fine EMFs, and restriction (mean) of fine cells and faces
- * into covered coarse cells and faces.  U_fine and U_coarse may be the same
- * state; registers are read from workspace and cleared. */
+ * substeps (the (S)ynchronise and (R)estrict of Sec. 4), from the registers
+ * in workspace: (1) reflux: each uncovered coarse cell next to covered ones
+ * gets U += (+-1/dx_d) (dt_c F_c - sum_k dt_f <F_f>_k) per coarse/fine face
+ * (sign + on its high face), <> the mean over the fine faces; (2) EMF
+ * correction: each copy of a coarse face with no covered neighbour gets
+ * B -= curl(dE) over the coarse/fine edges it touches, dE = sum_k dt_f
+ * <E_f>_k - dt_c E_c; (3) restriction: covered coarse cells and every copy of
+ * a coarse face with a covered neighbour take the mean of the fine cells or
+ * faces.  U_fine: the fine level's current buffer; U_coarse: the coarse
+ * level's current buffer (modified). */
 amr_status amr_restrict_fluxfix(amr_hierarchy* h, int32_t fine_level, const amr_state* U_fine,
                                 amr_state* U_coarse, void* workspace, void* stream);
+
+/* One coarse step of the whole hierarchy on `stream`: dt0 from the CFL
+ * reduction, level-0 fill, then the level cycle.
+ *   mode 0 (batched): R^(nlevels-1) launch cycles; before each, FULL or
+ *     SAME_LEVEL fills of the levels stepping in it (coarse to fine); one
+ *     batched advance of all of them (finest level first: the one-GPU form
+ *     of the paper's finest-first inter-level threading, Sec. 4); then the
+ *     syncs of every level that completed R substeps (fine to coarse).
+ *   mode 1 (per-grid): the paper's serial level order (0, 1, 2, 2, 1, 2, 2
+ *     for three levels, Sec. 4) with one launch per grid.
+ * Both modes produce bitwise identical results.  *parity (host) is read and
+ * updated; U_a / U_b as above. */
+amr_status amr_coarse_step(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t* parity, double* dt0,
+                           void* workspace, int32_t mode, void* stream);
 
 /* Discrete adjoint of nsteps single-level steps of one grid or all grids of
  * one level (limiter and Riemann branches frozen from the recomputed forward

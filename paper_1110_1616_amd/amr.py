@@ -61,13 +61,17 @@ def lib():
         L.amr_strerror.restype = C.c_char_p
         L.amr_create.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.POINTER(_VP)]
         L.amr_destroy.argtypes = [_VP]
+        L.amr_validate.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.POINTER(C.c_int64)]
         L.amr_layout.argtypes = [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.amr_load_primitive.argtypes = [_VP, C.c_int32, _PP, _PP, C.POINTER(amr_state), _VP]
         L.amr_store_interior.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), _PP, _VP]
-        L.amr_compute_dt.argtypes = [_VP, C.POINTER(amr_state), _VP, _VP, _VP]
-        L.amr_fill_ghosts_prolong.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(amr_state), _VP]
+        L.amr_compute_dt.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP]
+        L.amr_fill_ghosts_prolong.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state),
+                                              _VP]
         L.amr_advance_patches.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
-                                          C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP, _VP]
+                                          C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP, _VP]
+        L.amr_coarse_step.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.POINTER(C.c_uint32), _VP,
+                                      _VP, C.c_int32, _VP]
         L.amr_restrict_fluxfix.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP]
         L.amr_advance_adjoint.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
                                           C.POINTER(amr_state), _VP, _VP]
@@ -107,6 +111,39 @@ def amr_create(params, grids):
     return h
 
 
+def amr_validate(params, grids):
+    """Host-only validation and table build; returns the stats dict."""
+    arr = (amr_grid * len(grids))(*grids)
+    st = (C.c_int64 * 8)()
+    _check(lib().amr_validate(C.byref(params), arr, len(grids), st), "amr_validate")
+    keys = ("grids", "state_elems", "workspace_bytes", "copy_entries", "prolong_entries", "sync_entries",
+            "flux_items", "update_items")
+    return dict(zip(keys, list(st)))
+
+
+def make_params(ndim, domain, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0, 0), dx0=None, gamma=5.0 / 3.0,
+                cfl=0.4):
+    domain = tuple(domain) + (1,) * (3 - len(domain))
+    p = amr_params()
+    p.ndim, p.nlevels, p.ratio, p.ghost = ndim, nlevels, ratio, ghost
+    p.dtype = AMR_F64 if dtype == "f64" else AMR_F32
+    for d in range(3):
+        p.bc[d] = bc[d] if d < len(bc) else 0
+        p.domain[d] = domain[d]
+        p.dx0[d] = (dx0[d] if dx0 is not None else 1.0 / domain[d]) if d < ndim else 1.0
+    p.gamma, p.cfl = gamma, cfl
+    return p
+
+
+def make_grids(grids):
+    out = []
+    for lev, lo, hi in grids:
+        lo = tuple(lo) + (0,) * (3 - len(lo))
+        hi = tuple(hi) + (1,) * (3 - len(hi))
+        out.append(amr_grid(lev, (C.c_int32 * 3)(*lo), (C.c_int32 * 3)(*hi)))
+    return out
+
+
 def amr_destroy(h):
     _check(lib().amr_destroy(h), "amr_destroy")
 
@@ -130,22 +167,31 @@ def amr_store_interior(h, grid, U, outs):
     _check(lib().amr_store_interior(h, grid, C.byref(U), oo, _stream()), "amr_store_interior")
 
 
-def amr_compute_dt(h, U, dt0, ws):
-    _check(lib().amr_compute_dt(h, C.byref(U), _ptr(dt0), _ptr(ws), _stream()), "amr_compute_dt")
+def amr_compute_dt(h, Ua, Ub, parity, dt0):
+    _check(lib().amr_compute_dt(h, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _stream()), "amr_compute_dt")
 
 
-def amr_fill_ghosts_prolong(h, level, mode, U):
-    _check(lib().amr_fill_ghosts_prolong(h, level, mode, C.byref(U), _stream()), "amr_fill_ghosts_prolong")
+def amr_fill_ghosts_prolong(h, level, mode, U_level, U_parent=None):
+    up = C.byref(U_parent) if U_parent is not None else None
+    _check(lib().amr_fill_ghosts_prolong(h, level, mode, C.byref(U_level), up, _stream()), "amr_fill_ghosts_prolong")
 
 
-def amr_advance_patches(h, cycle, subset, band, Uin, Uout, dt0, ws):
+def amr_advance_patches(h, cycle, subset, band, Ua, Ub, parity, dt0, ws):
     if subset:
         arr = (C.c_int32 * len(subset))(*subset)
         n = len(subset)
     else:
         arr, n = None, 0
-    _check(lib().amr_advance_patches(h, cycle, arr, n, band, C.byref(Uin), C.byref(Uout), _ptr(dt0), _ptr(ws),
+    _check(lib().amr_advance_patches(h, cycle, arr, n, band, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws),
                                      _stream()), "amr_advance_patches")
+
+
+def amr_coarse_step(h, Ua, Ub, parity, dt0, ws, mode=0):
+    """One coarse step; returns the updated parity word."""
+    par = C.c_uint32(parity)
+    _check(lib().amr_coarse_step(h, C.byref(Ua), C.byref(Ub), C.byref(par), _ptr(dt0), _ptr(ws), mode, _stream()),
+           "amr_coarse_step")
+    return par.value
 
 
 def amr_restrict_fluxfix(h, fine_level, Ufine, Ucoarse, ws):
@@ -208,21 +254,9 @@ class Hierarchy:
         self.ghost = ghost
         self.gamma = gamma
         self.dtype = torch.float64 if dtype == "f64" else torch.float32
-        p = amr_params()
-        p.ndim, p.nlevels, p.ratio, p.ghost = ndim, nlevels, ratio, ghost
-        p.dtype = AMR_F64 if dtype == "f64" else AMR_F32
-        for d in range(3):
-            p.bc[d] = bc[d] if d < len(bc) else 0
-            p.domain[d] = self.domain[d]
-            p.dx0[d] = (dx0[d] if dx0 is not None else 1.0 / self.domain[d]) if d < ndim else 1.0
-        p.gamma, p.cfl = gamma, cfl
+        p = make_params(ndim, domain, nlevels, ratio, ghost, dtype, bc, dx0, gamma, cfl)
         self.params = p
-        self.grid_records = []
-        for g in grids:
-            lev, lo, hi = g
-            lo = tuple(lo) + (0,) * (3 - len(lo))
-            hi = tuple(hi) + (1,) * (3 - len(hi))
-            self.grid_records.append(amr_grid(lev, (C.c_int32 * 3)(*lo), (C.c_int32 * 3)(*hi)))
+        self.grid_records = make_grids(grids)
         self.grids = [(g.level, tuple(g.lo), tuple(g.hi)) for g in self.grid_records]
         self.h = amr_create(p, self.grid_records)
         self.state_elems, self.workspace_bytes, self.offsets = amr_layout(self.h, len(grids))
@@ -268,14 +302,21 @@ class Hierarchy:
         t.cuda.synchronize()
         return [o.cpu().numpy() for o in outs]
 
-    def compute_dt(self, U):
-        amr_compute_dt(self.h, U.c, self.dt0, self.ws)
+    def compute_dt(self, U, V=None, parity=0):
+        amr_compute_dt(self.h, U.c, (V or U).c, parity, self.dt0)
 
-    def fill(self, level, mode, U):
-        amr_fill_ghosts_prolong(self.h, level, mode, U.c)
+    def fill(self, level, mode, U, Up=None):
+        amr_fill_ghosts_prolong(self.h, level, mode, U.c, Up.c if Up is not None else None)
 
-    def advance(self, Uin, Uout, cycle=0, band=0, subset=None):
-        amr_advance_patches(self.h, -1 if subset else cycle, subset, band, Uin.c, Uout.c, self.dt0, self.ws)
+    def advance(self, Uin, Uout, cycle=0, band=0, subset=None, parity=0):
+        """Single-level style: parity 0 reads Uin and writes Uout."""
+        amr_advance_patches(self.h, -1 if subset else cycle, subset, band, Uin.c, Uout.c, parity, self.dt0, self.ws)
+
+    def coarse_step(self, Ua, Ub, parity, mode=0):
+        return amr_coarse_step(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, mode)
+
+    def current(self, Ua, Ub, parity, level):
+        return Ub if (parity >> level) & 1 else Ua
 
     def error_flags(self):
         return amr_get_error_flags(self.h)

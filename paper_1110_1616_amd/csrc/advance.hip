@@ -11,6 +11,7 @@
 // read each tile's grid descriptor, so one launch covers every grid that
 // steps in a launch cycle.
 #include "amr_internal.hpp"
+#include "emf.hpp"
 #include "mhd_device.hpp"
 
 namespace amr {
@@ -160,8 +161,8 @@ __device__ __forceinline__ void ring_entry(int r, int& ex, int& ey) {
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
-                                              int nitems, DevState<T> U, DevFlux<T> F,
-                                              const double* __restrict__ dt0p, Phys ph, ErrBlock* err) {
+                                              int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
+                                              DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err) {
   __shared__ T sW[8][kW * kW];
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
@@ -175,6 +176,8 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
+    // each level's current data lives in S0 or S1 (bit `level` of parity)
+    const DevState<T> U = ((parity >> G.level) & 1u) ? S1 : S0;
     const Idx<NDIM> ix(G);
     const int gv = item.gv;
     const int cl = -gv + 1;
@@ -306,26 +309,18 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
   }
 }
 
-// Edge EMF along axis A at the edge whose high-side cell index is e:
-// mean of the two adjacent B-face fluxes of each of the other two directions
-// (E_A = -F_b(B_c) on b-faces, +F_c(B_b) on c-faces, b = A+1, c = A+2).
-template <int A, class T>
-__device__ __forceinline__ T edge_emf(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
-  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
-  T s1 = F.f[B][5][e - st[C]] + F.f[B][5][e];
-  T s2 = F.f[C][6][e - st[B]] + F.f[C][6][e];
-  return T(0.25) * (s2 - s1);
-}
-
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
-                                                int nitems, DevState<T> Uin, DevState<T> Uout, DevFlux<T> F,
-                                                const double* __restrict__ dt0p, Phys ph) {
+                                                int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
+                                                DevFlux<T> F, const double* __restrict__ dt0p, Phys ph) {
   const int tx = threadIdx.x & 15;
   const int ty = threadIdx.x >> 4;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const UpdItem item = items[it];
     const GridDesc G = grids[item.grid];
+    const bool odd = (parity >> G.level) & 1u;
+    const DevState<T> Uin = odd ? S1 : S0;
+    const DevState<T> Uout = odd ? S0 : S1;
     const Idx<NDIM> ix(G);
     const int gv = item.gv;
     const int uhx = G.n[0] + gv - 2, uhy = G.n[1] + gv - 2, uhz = NDIM == 3 ? G.n[2] + gv - 2 : 0;
@@ -385,13 +380,8 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
           Uout.f[7][e] = Uin.f[7][e] - (cdx * (ey1 - ey0) - cdy * (ex1 - ex0));
         }
       } else {
-        // 2D: only E_z; edges are cell corners.  E_z = -F_x(By) on x-faces
-        // (x-flux t1 = y, index 5) and +F_y(Bx) on y-faces (y-flux t2 = x, index 6).
-        auto ez = [&](int64_t ee) {
-          T s1 = F.f[0][5][ee - st[1]] + F.f[0][5][ee];
-          T s2 = F.f[1][6][ee - st[0]] + F.f[1][6][ee];
-          return T(0.25) * (s2 - s1);
-        };
+        // 2D: only E_z; edges are cell corners.
+        auto ez = [&](int64_t ee) { return edge_emf<2>(F, ee, st); };
         if (cy < uhy) {  // Bx face
           T e0 = ez(e), e1 = ez(e + st[1]);
           Uout.f[5][e] = Uin.f[5][e] - cdy * (e1 - e0);
@@ -408,32 +398,36 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
 }  // namespace
 
 template <class T>
-void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> U, DevFlux<T> F,
-                 const double* dt0, Phys ph, ErrBlock* err, hipStream_t s) {
+void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
+                 uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, hipStream_t s) {
   if (nitems <= 0) return;
   if (ndim == 3)
-    hipLaunchKernelGGL((k_flux<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, F, dt0, ph, err);
+    hipLaunchKernelGGL((k_flux<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph,
+                       err);
   else
-    hipLaunchKernelGGL((k_flux<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, F, dt0, ph, err);
+    hipLaunchKernelGGL((k_flux<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph,
+                       err);
 }
 
 template <class T>
-void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> Uin,
-                   DevState<T> Uout, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s) {
+void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
+                   uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s) {
   if (nitems <= 0) return;
   if (ndim == 3)
-    hipLaunchKernelGGL((k_update<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, Uin, Uout, F, dt0, ph);
+    hipLaunchKernelGGL((k_update<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0,
+                       ph);
   else
-    hipLaunchKernelGGL((k_update<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, Uin, Uout, F, dt0, ph);
+    hipLaunchKernelGGL((k_update<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0,
+                       ph);
 }
 
-template void launch_flux<float>(int, const GridDesc*, const FluxItem*, int, DevState<float>, DevFlux<float>,
-                                 const double*, Phys, ErrBlock*, hipStream_t);
-template void launch_flux<double>(int, const GridDesc*, const FluxItem*, int, DevState<double>, DevFlux<double>,
-                                  const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_flux<float>(int, const GridDesc*, const FluxItem*, int, DevState<float>, DevState<float>,
+                                 uint32_t, DevFlux<float>, const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_flux<double>(int, const GridDesc*, const FluxItem*, int, DevState<double>, DevState<double>,
+                                  uint32_t, DevFlux<double>, const double*, Phys, ErrBlock*, hipStream_t);
 template void launch_update<float>(int, const GridDesc*, const UpdItem*, int, DevState<float>, DevState<float>,
-                                   DevFlux<float>, const double*, Phys, hipStream_t);
+                                   uint32_t, DevFlux<float>, const double*, Phys, hipStream_t);
 template void launch_update<double>(int, const GridDesc*, const UpdItem*, int, DevState<double>, DevState<double>,
-                                    DevFlux<double>, const double*, Phys, hipStream_t);
+                                    uint32_t, DevFlux<double>, const double*, Phys, hipStream_t);
 
 }  // namespace amr

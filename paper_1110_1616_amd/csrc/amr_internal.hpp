@@ -71,11 +71,13 @@ constexpr int kFluxTile = 15;  // owned cells per tile edge of the flux kernel
 constexpr int kUpdTile = 16;   // cells per tile edge of the update kernel
 
 // Host-side launchers (defined in the .hip translation units).
+// Level l of a grid reads its state from S1 if bit l of `parity` is set,
+// else from S0; the update writes the other one.
 template <class T>
-void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> U, DevFlux<T> F,
-                 const double* dt0, Phys ph, ErrBlock* err, hipStream_t s);
+void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
+                 uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, hipStream_t s);
 template <class T>
-void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> Uin,
-                   DevState<T> Uout, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s);
+void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
+                   uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s);
 
 }  // namespace amr

@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void k_copy(const CopyEntry* __restrict__ ent,
 // for the conserved cell fields (R = 2, s_d = +-1 the fine half).
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_prolong_cells(const ProlongEntry* __restrict__ ent, int n,
-                                                       const GridDesc* __restrict__ grids, DevState<T> U) {
+                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
+                                                       DevState<T> Ud) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const ProlongEntry e = ent[t];
     const GridDesc P = grids[e.pgrid];
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void k_prolong_cells(const ProlongEntry* __res
     for (int q = 0; q < 6; ++q) {
       if (q >= nfield) break;
       const int s = q < 5 ? q : 7;
-      const T* f = U.f[s];
+      const T* f = Us.f[s];
       const T c = f[e.src];
       T v = c;
 #pragma unroll
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_prolong_cells(const ProlongEntry* __res
         const T sg = ((e.code >> d) & 1) ? T(0.25) : T(-0.25);
         v += sg * sl;
       }
-      U.f[s][e.dst] = v;
+      Ud.f[s][e.dst] = v;
     }
   }
 }
@@ -78,8 +79,8 @@ __device__ __forceinline__ T tslope(const T* f, int64_t e, int64_t s) {
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __restrict__ ent, int n,
-                                                       const GridDesc* __restrict__ grids, DevState<T> U,
-                                                       Phys ph) {
+                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
+                                                       DevState<T> Ud, Phys ph) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const ProlongEntry e = ent[t];
     const GridDesc P = grids[e.pgrid];
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __res
     const T s2 = ((e.code >> 4) & 1) ? T(1) : T(-1);
     const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
     const bool act1 = a1 < NDIM, act2 = a2 < NDIM;
-    const T* fd = U.f[5 + d];
+    const T* fd = Us.f[5 + d];
     T v;
     if (!mid) {
       v = fd[e.src];
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __res
       for (int tt = 1; tt <= 2; ++tt) {
         const int ta = (d + tt) % 3;
         if (ta >= NDIM) continue;
-        const T* ft = U.f[5 + ta];
+        const T* ft = Us.f[5 + ta];
         const T sp = tslope<T, NDIM>(ft, e.src + st[ta], st[d]);
         const T sm = tslope<T, NDIM>(ft, e.src, st[d]);
         add += T(0.25) * (sp - sm) / wdt[ta];
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __res
       const T a0 = T(0.5) * (bp + bm) - add;
       v = a0 + T(0.5) * s1 * ay + T(0.5) * s2 * az;
     }
-    U.f[5 + d][e.dst] = v;
+    Ud.f[5 + d][e.dst] = v;
   }
 }
 
@@ -138,8 +139,8 @@ __device__ __forceinline__ double wave_max(double v) {
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids, const int4* __restrict__ items,
-                                             int nitems, DevState<T> U, Phys ph, unsigned long long* acc,
-                                             ErrBlock* err) {
+                                             int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity, Phys ph,
+                                             unsigned long long* acc, ErrBlock* err) {
   __shared__ double red[4];
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids,
     // item: (grid, plane k, first row j0, rows)
     const int4 item = items[it];
     const GridDesc G = grids[item.x];
+    const DevState<T> U = ((parity >> G.level) & 1u) ? S1 : S0;
     const int k = item.y;
     const int64_t sy = G.P[0], sz = (int64_t)G.P[0] * G.P[1];
     const int64_t base = G.off + G.g + G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0) + (int64_t)k * sz +
@@ -288,31 +290,36 @@ void launch_copy(int ndim, const CopyEntry* ent, int n, int4 cls, DevState<T> U,
 
 template <class T>
 void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const ProlongEntry* faces, int nfaces,
-                    const GridDesc* grids, DevState<T> U, Phys ph, hipStream_t s) {
+                    const GridDesc* grids, DevState<T> Us, DevState<T> Ud, Phys ph, hipStream_t s) {
   if (ncells > 0) {
     if (ndim == 3)
-      hipLaunchKernelGGL((k_prolong_cells<T, 3>), dim3(blocks_for(ncells)), dim3(256), 0, s, cells, ncells, grids, U);
+      hipLaunchKernelGGL((k_prolong_cells<T, 3>), dim3(blocks_for(ncells)), dim3(256), 0, s, cells, ncells, grids, Us,
+                         Ud);
     else
-      hipLaunchKernelGGL((k_prolong_cells<T, 2>), dim3(blocks_for(ncells)), dim3(256), 0, s, cells, ncells, grids, U);
+      hipLaunchKernelGGL((k_prolong_cells<T, 2>), dim3(blocks_for(ncells)), dim3(256), 0, s, cells, ncells, grids, Us,
+                         Ud);
   }
   if (nfaces > 0) {
     if (ndim == 3)
-      hipLaunchKernelGGL((k_prolong_faces<T, 3>), dim3(blocks_for(nfaces)), dim3(256), 0, s, faces, nfaces, grids, U,
-                         ph);
+      hipLaunchKernelGGL((k_prolong_faces<T, 3>), dim3(blocks_for(nfaces)), dim3(256), 0, s, faces, nfaces, grids, Us,
+                         Ud, ph);
     else
-      hipLaunchKernelGGL((k_prolong_faces<T, 2>), dim3(blocks_for(nfaces)), dim3(256), 0, s, faces, nfaces, grids, U,
-                         ph);
+      hipLaunchKernelGGL((k_prolong_faces<T, 2>), dim3(blocks_for(nfaces)), dim3(256), 0, s, faces, nfaces, grids, Us,
+                         Ud, ph);
   }
 }
 
 template <class T>
-void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> U, Phys ph,
-                unsigned long long* acc, ErrBlock* err, double cfl, double* dt0, hipStream_t s) {
+void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> S0, DevState<T> S1,
+                uint32_t parity, Phys ph, unsigned long long* acc, ErrBlock* err, double cfl, double* dt0,
+                hipStream_t s) {
   if (nitems > 0) {
     if (ndim == 3)
-      hipLaunchKernelGGL((k_cfl<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, ph, acc, err);
+      hipLaunchKernelGGL((k_cfl<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, ph, acc,
+                         err);
     else
-      hipLaunchKernelGGL((k_cfl<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, U, ph, acc, err);
+      hipLaunchKernelGGL((k_cfl<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, ph, acc,
+                         err);
   }
   hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(64), 0, s, acc, cfl, dt0);
 }
@@ -343,9 +350,9 @@ void launch_store(int ndim, const GridDesc& G, DevState<T> U, double* const* out
 #define AMR_INST(T)                                                                                              \
   template void launch_copy<T>(int, const CopyEntry*, int, int4, DevState<T>, hipStream_t);                       \
   template void launch_prolong<T>(int, const ProlongEntry*, int, const ProlongEntry*, int, const GridDesc*,       \
-                                  DevState<T>, Phys, hipStream_t);                                                \
-  template void launch_cfl<T>(int, const GridDesc*, const int4*, int, DevState<T>, Phys, unsigned long long*,     \
-                              ErrBlock*, double, double*, hipStream_t);                                           \
+                                  DevState<T>, DevState<T>, Phys, hipStream_t);                                   \
+  template void launch_cfl<T>(int, const GridDesc*, const int4*, int, DevState<T>, DevState<T>, uint32_t, Phys,   \
+                              unsigned long long*, ErrBlock*, double, double*, hipStream_t);                      \
   template void launch_load_prim<T>(int, const GridDesc&, const double* const*, const double* const*,            \
                                     DevState<T>, double, hipStream_t);                                            \
   template void launch_store<T>(int, const GridDesc&, DevState<T>, double* const*, hipStream_t);

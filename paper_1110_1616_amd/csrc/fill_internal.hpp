@@ -23,12 +23,14 @@ struct ProlongEntry {
 
 template <class T>
 void launch_copy(int ndim, const CopyEntry* ent, int n, int4 cls, DevState<T> U, hipStream_t s);
+// Prolongation reads the parent level from Us and writes the band into Ud.
 template <class T>
 void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const ProlongEntry* faces, int nfaces,
-                    const GridDesc* grids, DevState<T> U, Phys ph, hipStream_t s);
+                    const GridDesc* grids, DevState<T> Us, DevState<T> Ud, Phys ph, hipStream_t s);
 template <class T>
-void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> U, Phys ph,
-                unsigned long long* acc, ErrBlock* err, double cfl, double* dt0, hipStream_t s);
+void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> S0, DevState<T> S1,
+                uint32_t parity, Phys ph, unsigned long long* acc, ErrBlock* err, double cfl, double* dt0,
+                hipStream_t s);
 template <class T>
 void launch_load_prim(int ndim, const GridDesc& G, const double* const* prim, const double* const* b,
                       DevState<T> U, double gamma, hipStream_t s);

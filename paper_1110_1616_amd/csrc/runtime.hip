@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -39,8 +40,11 @@ struct Error : std::runtime_error {
 
 #define HIPCHK_NOTHROW(x) (void)(x)
 
+// When set, table builders run on the host only (amr_validate).
+thread_local bool g_host_only = false;
+
 template <class T> T* dev_upload(const std::vector<T>& v) {
-  if (v.empty()) return nullptr;
+  if (v.empty() || g_host_only) return nullptr;
   T* p = nullptr;
   HIPCHK(hipMalloc((void**)&p, v.size() * sizeof(T)));
   HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -184,8 +188,15 @@ struct LevelIndex {
   }
 };
 
+// Pool element of (i, j, k) in grid G; every table entry goes through here,
+// so an index outside the grid's padded box is caught on the host.
 int64_t elem(const GridDesc& G, int ndim, int i, int j, int k) {
   const int gz = ndim == 3 ? G.g : 0;
+  const int x[3] = {i, j, k};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = a < ndim ? -G.g : 0, hi = a < ndim ? G.n[a] + G.g : 0;
+    if (x[a] < lo || x[a] > hi) throw Error(AMR_EINVAL, "internal: table element outside its grid's box");
+  }
   return G.off + (int64_t)(i + G.g) + (int64_t)(j + G.g) * G.P[0] + (int64_t)(k + gz) * G.P[0] * G.P[1];
 }
 
@@ -452,6 +463,9 @@ void build_fill_maps(amr_hierarchy* h) {
                 const amr_grid& PG = h->grids[pg];
                 int code = 0;
                 for (int a = 0; a < nd; ++a) code |= (posmod(gpos[a], 2) << a);
+                for (int a = 0; a < nd; ++a)
+                  if (cc[a] - PG.lo[a] < -P.g + 1 || cc[a] - PG.lo[a] > P.n[a] + P.g - 2)
+                    throw Error(AMR_EINVAL, "internal: prolongation stencil leaves the parent box");
                 pc.push_back(ProlongEntry{(int32_t)dst,
                                           (int32_t)elem(P, nd, cc[0] - PG.lo[0], cc[1] - PG.lo[1], cc[2] - PG.lo[2]),
                                           pg, code});
@@ -482,6 +496,9 @@ void build_fill_maps(amr_hierarchy* h) {
                 const GridDesc& P = h->desc[pg];
                 const amr_grid& PG = h->grids[pg];
                 const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+                for (int a = 0; a < nd; ++a)
+                  if (w[a] - PG.lo[a] < -P.g + 1 || w[a] - PG.lo[a] > P.n[a] + P.g - 2)
+                    throw Error(AMR_EINVAL, "internal: prolongation stencil leaves the parent box");
                 int code = d | (mid ? 4 : 0);
                 if (a1 < nd && posmod(gpos[a1], 2)) code |= 8;
                 if (a2 < nd && posmod(gpos[a2], 2)) code |= 16;
@@ -547,6 +564,239 @@ void check_nesting(amr_hierarchy* h) {
   }
 }
 
+
+// ------------------------------------------------------------ sync tables
+// Coarse/fine registers, reflux, EMF-fix and restriction entries of fine
+// level f (see sync_internal.hpp).  Positions on periodic levels are taken in
+// the frame of the grid that stores them.
+void build_sync_tables(amr_hierarchy* h, int f) {
+  const int nd = h->ndim, R = h->R, c = f - 1;
+  LevelIndex CI, FI;
+  CI.build(h, c);
+  FI.build(h, f);
+  auto covered = [&](const int (&pc)[3]) {
+    int pf[3];
+    for (int a = 0; a < 3; ++a) pf[a] = a < nd ? R * pc[a] : 0;
+    if (!FI.wrap(pf)) return false;
+    return FI.find_cell(pf) >= 0;
+  };
+  // fine grid owning fine cell p (unwrapped); shift = wrap(p) - p
+  auto fine_owner = [&](const int (&p)[3], int (&shift)[3]) {
+    int w[3] = {p[0], p[1], p[2]};
+    if (!FI.wrap(w)) return -1;
+    for (int a = 0; a < 3; ++a) shift[a] = w[a] - p[a];
+    return FI.find_cell(w);
+  };
+  const double dxc[3] = {h->p.dx0[0] / ipow(R, c), h->p.dx0[1] / ipow(R, c), nd == 3 ? h->p.dx0[2] / ipow(R, c) : 1.0};
+  SyncTables& T = h->sync[f];
+  std::vector<FaceRegEntry> frc, frf;
+  std::vector<EdgeRegEntry> erc, erf;
+  std::vector<RefluxEntry> rfx;
+  std::vector<EmfFixEntry> efx;
+  std::vector<RestrictEntry> rst;
+  std::map<std::vector<int>, int> edge_id;
+  int nfreg = 0;
+
+  for (int gi : h->level_grids[c]) {
+    const GridDesc& C = h->desc[gi];
+    const amr_grid& CG = h->grids[gi];
+    // cells: restriction or reflux
+    for (int k = 0; k < C.n[2]; ++k)
+      for (int j = 0; j < C.n[1]; ++j)
+        for (int i = 0; i < C.n[0]; ++i) {
+          int pu[3] = {CG.lo[0] + i, CG.lo[1] + j, CG.lo[2] + k};
+          if (covered(pu)) {
+            int pf[3], sh[3];
+            for (int a = 0; a < 3; ++a) pf[a] = a < nd ? R * pu[a] : 0;
+            int fg = fine_owner(pf, sh);
+            const amr_grid& FG = h->grids[fg];
+            rst.push_back(RestrictEntry{(int32_t)elem(C, nd, i, j, k),
+                                        (int32_t)elem(h->desc[fg], nd, pf[0] + sh[0] - FG.lo[0],
+                                                      pf[1] + sh[1] - FG.lo[1], pf[2] + sh[2] - FG.lo[2]),
+                                        fg, -1});
+            continue;
+          }
+          RefluxEntry re{};
+          re.cell = (int32_t)elem(C, nd, i, j, k);
+          for (int d = 0; d < nd; ++d)
+            for (int side = -1; side <= 1; side += 2) {
+              int pv[3] = {pu[0], pu[1], pu[2]};
+              pv[d] += side;
+              if (!covered(pv)) continue;
+              int lf[3] = {i, j, k};
+              if (side > 0) lf[d] += 1;
+              const int r = nfreg++;
+              FaceRegEntry ec{};
+              ec.reg = r;
+              ec.d = d;
+              ec.grid = gi;
+              ec.n = 1;
+              ec.e[0] = (int32_t)elem(C, nd, lf[0], lf[1], lf[2]);
+              frc.push_back(ec);
+              // fine faces on the coarse face, in the frame of their grid
+              int fc[3];
+              for (int a = 0; a < 3; ++a) fc[a] = a < nd ? R * pv[a] : 0;
+              if (side < 0) fc[d] += R - 1;
+              int sh[3];
+              int fg = fine_owner(fc, sh);
+              if (fg < 0) throw Error(AMR_EINVAL, "internal: covered cell without fine owner");
+              const amr_grid& FG = h->grids[fg];
+              FaceRegEntry ef{};
+              ef.reg = r;
+              ef.d = d;
+              ef.grid = fg;
+              int gf[3];
+              for (int a = 0; a < 3; ++a) gf[a] = a < nd ? R * (CG.lo[a] + lf[a]) + sh[a] : 0;
+              const int o1 = (d + 1) % 3, o2 = (d + 2) % 3;
+              for (int a1 = 0; a1 < (o1 < nd ? R : 1); ++a1)
+                for (int a2 = 0; a2 < (o2 < nd ? R : 1); ++a2) {
+                  int p[3] = {gf[0], gf[1], gf[2]};
+                  p[o1] += a1;
+                  p[o2] += a2;
+                  ef.e[ef.n++] = (int32_t)elem(h->desc[fg], nd, p[0] - FG.lo[0], p[1] - FG.lo[1], p[2] - FG.lo[2]);
+                }
+              frf.push_back(ef);
+              re.reg[re.n] = r;
+              re.coef[re.n] = (side > 0 ? 1.0 : -1.0) / dxc[d];
+              ++re.n;
+            }
+          if (re.n > 0) rfx.push_back(re);
+        }
+    // faces: restriction (a covered neighbour) or EMF fix (C/F edges)
+    for (int d = 0; d < nd; ++d) {
+      for (int k = 0; k < C.n[2] + (d == 2 ? 1 : 0); ++k)
+        for (int j = 0; j < C.n[1] + (d == 1 ? 1 : 0); ++j)
+          for (int i = 0; i < C.n[0] + (d == 0 ? 1 : 0); ++i) {
+            int pf[3] = {CG.lo[0] + i, CG.lo[1] + j, CG.lo[2] + k};
+            int pm[3] = {pf[0], pf[1], pf[2]};
+            pm[d] -= 1;
+            const bool cu = covered(pf), cm = covered(pm);
+            if (cu || cm) {
+              // fine faces from the lowest-id fine grid owning a neighbour
+              int best = -1, bsh[3] = {0, 0, 0};
+              for (int side = 0; side < 2; ++side) {
+                if ((side == 0 && !cu) || (side == 1 && !cm)) continue;
+                int fc[3];
+                for (int a = 0; a < 3; ++a) fc[a] = a < nd ? R * pf[a] : 0;
+                if (side == 1) fc[d] -= 1;
+                int sh[3];
+                int fg = fine_owner(fc, sh);
+                if (fg >= 0 && (best < 0 || fg < best)) {
+                  best = fg;
+                  for (int a = 0; a < 3; ++a) bsh[a] = sh[a];
+                }
+              }
+              const amr_grid& FG = h->grids[best];
+              int q[3];
+              for (int a = 0; a < 3; ++a) q[a] = a < nd ? R * pf[a] + bsh[a] - FG.lo[a] : 0;
+              rst.push_back(RestrictEntry{(int32_t)elem(C, nd, i, j, k),
+                                          (int32_t)elem(h->desc[best], nd, q[0], q[1], q[2]), best, d});
+              continue;
+            }
+            // (curl dE)_d = d_b dE_cc - d_cc dE_b with b = d+1, cc = d+2
+            EmfFixEntry fx{};
+            fx.face = (int32_t)elem(C, nd, i, j, k);
+            fx.d = d;
+            const int b = (d + 1) % 3, cc = (d + 2) % 3;
+            for (int term = 0; term < 2; ++term) {
+              const int ea = term == 0 ? cc : b;
+              const int da = term == 0 ? b : cc;
+              if (da >= nd) continue;
+              if (nd == 2 && ea != 2) continue;
+              const double sgn = term == 0 ? 1.0 : -1.0;
+              for (int up = 0; up < 2; ++up) {
+                int e[3] = {pf[0], pf[1], pf[2]};
+                e[da] += up;
+                // neighbouring coarse cells of the edge (offsets -1/0 in the
+                // two axes other than ea)
+                const int b2 = (ea + 1) % 3, c2 = (ea + 2) % 3;
+                int ncov = 0, nall = 0, fg = -1, fsh[3] = {0, 0, 0}, fcell[3] = {0, 0, 0};
+                for (int db = 0; db < 2; ++db)
+                  for (int dc = 0; dc < 2; ++dc) {
+                    if ((b2 >= nd && db) || (c2 >= nd && dc)) continue;
+                    int p[3] = {e[0], e[1], e[2]};
+                    if (b2 < nd) p[b2] -= db;
+                    if (c2 < nd) p[c2] -= dc;
+                    ++nall;
+                    if (!covered(p)) continue;
+                    ++ncov;
+                    int fc[3];
+                    for (int a = 0; a < 3; ++a) fc[a] = a < nd ? R * p[a] : 0;
+                    int sh[3];
+                    int o = fine_owner(fc, sh);
+                    if (o >= 0 && (fg < 0 || o < fg)) {
+                      fg = o;
+                      for (int a = 0; a < 3; ++a) {
+                        fsh[a] = sh[a];
+                        fcell[a] = fc[a];
+                      }
+                    }
+                  }
+                (void)fcell;
+                if (!(ncov > 0 && ncov < nall)) continue;
+                // dedupe registers by (axis, wrapped edge index)
+                int w[3] = {e[0], e[1], e[2]};
+                for (int a = 0; a < nd; ++a) w[a] = posmod(w[a], CI.N[a]);
+                std::vector<int> key = {ea, w[0], w[1], w[2]};
+                int re;
+                auto it = edge_id.find(key);
+                if (it == edge_id.end()) {
+                  re = (int)edge_id.size();
+                  edge_id[key] = re;
+                  EdgeRegEntry ec{};
+                  ec.reg = re;
+                  ec.a = ea;
+                  ec.grid = gi;
+                  ec.n = 1;
+                  ec.e[0] = (int32_t)elem(C, nd, e[0] - CG.lo[0], e[1] - CG.lo[1], e[2] - CG.lo[2]);
+                  erc.push_back(ec);
+                  const amr_grid& FG = h->grids[fg];
+                  EdgeRegEntry ef{};
+                  ef.reg = re;
+                  ef.a = ea;
+                  ef.grid = fg;
+                  const int na = ea < nd ? R : 1;
+                  for (int s2 = 0; s2 < na; ++s2) {
+                    int p[3];
+                    for (int a = 0; a < 3; ++a) p[a] = a < nd ? R * e[a] + fsh[a] - FG.lo[a] : 0;
+                    if (ea < nd) p[ea] += s2;
+                    ef.e[ef.n++] = (int32_t)elem(h->desc[fg], nd, p[0], p[1], p[2]);
+                  }
+                  erf.push_back(ef);
+                } else {
+                  re = it->second;
+                }
+                if (fx.n >= 4) throw Error(AMR_EINVAL, "internal: more than 4 edges on a face");
+                fx.reg[fx.n] = re;
+                fx.coef[fx.n] = sgn * (up ? 1.0 : -1.0) / dxc[da];
+                ++fx.n;
+              }
+            }
+            if (fx.n > 0) efx.push_back(fx);
+          }
+    }
+  }
+  T.nfreg = nfreg;
+  T.nereg = (int)edge_id.size();
+  T.d_freg_c = dev_upload(frc);
+  T.n_freg_c = (int)frc.size();
+  T.d_freg_f = dev_upload(frf);
+  T.n_freg_f = (int)frf.size();
+  T.d_ereg_c = dev_upload(erc);
+  T.n_ereg_c = (int)erc.size();
+  T.d_ereg_f = dev_upload(erf);
+  T.n_ereg_f = (int)erf.size();
+  T.d_reflux = dev_upload(rfx);
+  T.n_reflux = (int)rfx.size();
+  T.d_emffix = dev_upload(efx);
+  T.n_emffix = (int)efx.size();
+  T.d_restrict = dev_upload(rst);
+  T.n_restrict = (int)rst.size();
+  const int64_t fbytes = (int64_t)(1 + R) * nfreg * 6 * (int64_t)h->esize;
+  const int64_t ebytes = (int64_t)(1 + R) * T.nereg * (int64_t)h->esize;
+  T.reg_bytes = (fbytes + 255) / 256 * 256 + ebytes;
+}
+
 template <class T> DevState<T> dstate(const amr_state* s) {
   DevState<T> d;
   for (int i = 0; i < 8; ++i) d.f[i] = (T*)s->f[i];
@@ -578,9 +828,9 @@ amr_status fail(const std::exception& e) {
 }
 
 template <class T>
-void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Uin, amr_state* Uout, const double* dt0,
-              void* ws, hipStream_t s) {
-  DevState<T> ui = dstate<T>(Uin), uo = dstate<T>(Uout);
+void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const amr_state* Ub, uint32_t parity,
+              const double* dt0, void* ws, hipStream_t s) {
+  DevState<T> s0 = dstate<T>(Ua), s1 = dstate<T>(Ub);
   DevFlux<T> F = dflux<T>(h, ws);
   Phys ph = phys(h);
   int e0 = 0, e1 = 0, e2 = 0;
@@ -590,15 +840,114 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Uin, amr_s
     e2 = h->take_event();
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
-  launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, ui, F, dt0, ph, h->d_err, s);
+  launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err, s);
   HIPCHK(hipGetLastError());
   if (h->timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
-  launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, ui, uo, F, dt0, ph, s);
+  launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, s);
   HIPCHK(hipGetLastError());
   if (h->timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
     h->ev_pairs[0].push_back({e0, e1});
     h->ev_pairs[1].push_back({e1, e2});
+  }
+}
+
+// Registers written after level l stepped at its substep k: the coarse side
+// of the sync with level l+1 and the fine side (slot 1 + k mod R) of the sync
+// with level l-1.
+template <class T>
+void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws, hipStream_t s) {
+  DevFlux<T> F = dflux<T>(h, ws);
+  const double div = (double)ipow(h->R, l);
+  if (l + 1 < h->nlev) {
+    const SyncTables& t = h->sync[l + 1];
+    T* freg = (T*)((char*)ws + t.reg_off);
+    T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
+    launch_registers<T>(h->ndim, h->d_desc, t.d_freg_c, t.n_freg_c, t.d_ereg_c, t.n_ereg_c, F, freg, ereg, t.nfreg,
+                        t.nereg, 0, dt0, div, s);
+    HIPCHK(hipGetLastError());
+  }
+  if (l >= 1) {
+    const SyncTables& t = h->sync[l];
+    T* freg = (T*)((char*)ws + t.reg_off);
+    T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
+    launch_registers<T>(h->ndim, h->d_desc, t.d_freg_f, t.n_freg_f, t.d_ereg_f, t.n_ereg_f, F, freg, ereg, t.nfreg,
+                        t.nereg, 1 + k % h->R, dt0, div, s);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+template <class T>
+void do_sync(amr_hierarchy* h, int f, const amr_state* Uf, amr_state* Uc, void* ws, hipStream_t s) {
+  const SyncTables& t = h->sync[f];
+  const T* freg = (const T*)((char*)ws + t.reg_off);
+  const T* ereg =
+      (const T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
+  launch_sync<T>(h->ndim, h->R, h->d_desc, t, freg, ereg, dstate<T>(Uf), dstate<T>(Uc), s);
+  HIPCHK(hipGetLastError());
+}
+
+template <class T>
+void do_fill(amr_hierarchy* h, int level, int mode, amr_state* Ul, const amr_state* Up, hipStream_t s) {
+  launch_copy<T>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<T>(Ul), s);
+  if (mode == AMR_FILL_FULL && level > 0)
+    launch_prolong<T>(h->ndim, h->d_pcell[level], h->n_pcell[level], h->d_pface[level], h->n_pface[level], h->d_desc,
+                      dstate<T>(Up), dstate<T>(Ul), phys(h), s);
+  HIPCHK(hipGetLastError());
+}
+
+template <class T>
+void do_dt(amr_hierarchy* h, const amr_state* Ua, const amr_state* Ub, uint32_t parity, double* dt0, hipStream_t s) {
+  unsigned long long* acc = (unsigned long long*)((char*)h->d_err + 64);
+  launch_cfl<T>(h->ndim, h->d_desc, h->d_cfl, h->n_cfl, dstate<T>(Ua), dstate<T>(Ub), parity, phys(h), acc, h->d_err,
+                h->p.cfl, dt0, s);
+  HIPCHK(hipGetLastError());
+}
+
+// One coarse step of the whole hierarchy.  mode 0: batched launch cycles
+// (every level stepping in a cycle in one launch, finest level first); mode
+// 1: the serial level order with one launch per grid (the per-grid path).
+template <class T>
+void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, double* dt0, void* ws, int mode,
+                 hipStream_t s) {
+  const int L = h->nlev, R = h->R;
+  auto cur = [&](int l) { return ((par >> l) & 1u) ? Ub : Ua; };
+  do_dt<T>(h, Ua, Ub, par, dt0, s);
+  do_fill<T>(h, 0, AMR_FILL_SAME_LEVEL, cur(0), cur(0), s);
+  if (mode == 0) {
+    const int ncyc = ipow(R, L - 1);
+    for (int c = 0; c < ncyc; ++c) {
+      uint32_t stepping = 0;
+      for (int l = 0; l < L; ++l) {
+        const int span = ipow(R, L - 1 - l);
+        if (c % span) continue;
+        stepping |= 1u << l;
+        const int k = c / span;
+        if (l > 0) do_fill<T>(h, l, (k % R == 0) ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s);
+      }
+      run_list<T>(h, h->cycle_lists[c], Ua, Ub, par, dt0, ws, s);
+      for (int l = 0; l < L; ++l)
+        if (stepping >> l & 1u) write_registers<T>(h, l, c / ipow(R, L - 1 - l), dt0, ws, s);
+      par ^= stepping;
+      for (int f = L - 1; f >= 1; --f)
+        if ((c + 1) % ipow(R, L - f) == 0) do_sync<T>(h, f, cur(f), cur(f - 1), ws, s);
+    }
+  } else {
+    std::function<void(int, int)> cyc = [&](int l, int k) {
+      if (l + 1 < L) do_fill<T>(h, l + 1, AMR_FILL_FULL, cur(l + 1), cur(l), s);
+      const int band = l == 0 ? h->g : h->g - 2 * (k % R);
+      for (int gi : h->level_grids[l]) run_list<T>(h, h->grid_lists.at({gi, band}), Ua, Ub, par, dt0, ws, s);
+      write_registers<T>(h, l, k, dt0, ws, s);
+      par ^= 1u << l;
+      if (l + 1 < L) {
+        for (int kk = 0; kk < R; ++kk) {
+          if (kk > 0) do_fill<T>(h, l + 1, AMR_FILL_SAME_LEVEL, cur(l + 1), cur(l), s);
+          cyc(l + 1, kk);
+        }
+        do_sync<T>(h, l + 1, cur(l + 1), cur(l), ws, s);
+      }
+    };
+    cyc(0, 0);
   }
 }
 
@@ -620,13 +969,13 @@ const char* amr_strerror(amr_status s) {
   return "unknown status";
 }
 
-amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids, amr_hierarchy** out) {
-  if (out) *out = nullptr;
-  amr_hierarchy* h = nullptr;
+namespace {
+// Validate and build every table of a hierarchy (device uploads skipped in
+// host-only mode).
+amr_hierarchy* build_hierarchy(const amr_params* p, const amr_grid* grids, int32_t ngrids) {
+  validate(p, grids, ngrids);
+  amr_hierarchy* h = new amr_hierarchy();
   try {
-    if (!out) throw Error(AMR_EINVAL, "out is NULL");
-    validate(p, grids, ngrids);
-    h = new amr_hierarchy();
     h->p = *p;
     h->ndim = p->ndim;
     h->nlev = p->nlevels;
@@ -664,16 +1013,67 @@ amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids
     build_lists(h);
     h->sync.resize(h->nlev);
     int64_t reg_bytes = 0;
-    for (int l = 1; l < h->nlev; ++l) reg_bytes += build_sync_tables(h->ndim, h->R, h->desc, h->grids, h->level_grids,
-                                                                     h->p, l, h->sync[l], h->reg_offset + reg_bytes,
-                                                                     h->esize);
+    for (int l = 1; l < h->nlev; ++l) {
+      build_sync_tables(h, l);
+      h->sync[l].reg_off = h->reg_offset + reg_bytes;
+      reg_bytes += (h->sync[l].reg_bytes + 255) / 256 * 256;
+    }
     h->workspace_bytes = h->reg_offset + reg_bytes;
+    return h;
+  } catch (...) {
+    delete h;
+    throw;
+  }
+}
+}  // namespace
+
+amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids, amr_hierarchy** out) {
+  if (out) *out = nullptr;
+  amr_hierarchy* h = nullptr;
+  try {
+    if (!out) throw Error(AMR_EINVAL, "out is NULL");
+    g_host_only = false;
+    h = build_hierarchy(p, grids, ngrids);
     HIPCHK(hipMalloc((void**)&h->d_err, 256));
     HIPCHK(hipMemset(h->d_err, 0, 256));
     HIPCHK(hipDeviceSynchronize());
     *out = h;
     return AMR_OK;
   } catch (const std::exception& e) {
+    delete h;
+    return fail(e);
+  }
+}
+
+amr_status amr_validate(const amr_params* p, const amr_grid* grids, int32_t ngrids, int64_t* stats) {
+  amr_hierarchy* h = nullptr;
+  try {
+    g_host_only = true;
+    h = build_hierarchy(p, grids, ngrids);
+    g_host_only = false;
+    if (stats) {
+      int64_t ncopy = 0, npro = 0, nsync = 0;
+      for (int l = 0; l < h->nlev; ++l) {
+        ncopy += h->n_copy[l];
+        npro += h->n_pcell[l] + h->n_pface[l];
+      }
+      for (int l = 1; l < h->nlev; ++l) {
+        const SyncTables& t = h->sync[l];
+        nsync += t.n_freg_c + t.n_freg_f + t.n_ereg_c + t.n_ereg_f + t.n_reflux + t.n_emffix + t.n_restrict;
+      }
+      stats[0] = (int64_t)h->grids.size();
+      stats[1] = h->total_elems;
+      stats[2] = h->workspace_bytes;
+      stats[3] = ncopy;
+      stats[4] = npro;
+      stats[5] = nsync;
+      stats[6] = (int64_t)h->h_fitems.size();
+      stats[7] = (int64_t)h->h_uitems.size();
+    }
+    delete h;
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    g_host_only = false;
     delete h;
     return fail(e);
   }
@@ -730,44 +1130,33 @@ amr_status amr_store_interior(amr_hierarchy* h, int32_t grid, const amr_state* U
   }
 }
 
-amr_status amr_compute_dt(amr_hierarchy* h, const amr_state* U, double* dt0, void* workspace, void* stream) {
+amr_status amr_compute_dt(amr_hierarchy* h, const amr_state* U_a, const amr_state* U_b, uint32_t parity,
+                          double* dt0, void* stream) {
   try {
-    if (!h || !U || !dt0) throw Error(AMR_EINVAL, "null argument");
-    (void)workspace;
+    if (!h || !U_a || !U_b || !dt0) throw Error(AMR_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long* acc = (unsigned long long*)((char*)h->d_err + 64);
     if (h->esize == 8)
-      launch_cfl<double>(h->ndim, h->d_desc, h->d_cfl, h->n_cfl, dstate<double>(U), phys(h), acc, h->d_err, h->p.cfl,
-                         dt0, s);
+      do_dt<double>(h, U_a, U_b, parity, dt0, s);
     else
-      launch_cfl<float>(h->ndim, h->d_desc, h->d_cfl, h->n_cfl, dstate<float>(U), phys(h), acc, h->d_err, h->p.cfl,
-                        dt0, s);
-    HIPCHK(hipGetLastError());
+      do_dt<float>(h, U_a, U_b, parity, dt0, s);
     return AMR_OK;
   } catch (const std::exception& e) {
     return fail(e);
   }
 }
 
-amr_status amr_fill_ghosts_prolong(amr_hierarchy* h, int32_t level, int32_t mode, amr_state* U, void* stream) {
+amr_status amr_fill_ghosts_prolong(amr_hierarchy* h, int32_t level, int32_t mode, amr_state* U_level,
+                                   const amr_state* U_parent, void* stream) {
   try {
-    if (!h || !U) throw Error(AMR_EINVAL, "null argument");
+    if (!h || !U_level) throw Error(AMR_EINVAL, "null argument");
     if (level < 0 || level >= h->nlev) throw Error(AMR_EINVAL, "level out of range");
     if (mode != AMR_FILL_FULL && mode != AMR_FILL_SAME_LEVEL) throw Error(AMR_EINVAL, "bad fill mode");
+    if (mode == AMR_FILL_FULL && level > 0 && !U_parent) throw Error(AMR_EINVAL, "FULL fill needs the parent state");
     hipStream_t s = (hipStream_t)stream;
-    // copies first, then prolongation (prolongation reads only the parent level)
-    if (h->esize == 8) {
-      launch_copy<double>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<double>(U), s);
-      if (mode == AMR_FILL_FULL && level > 0)
-        launch_prolong<double>(h->ndim, h->d_pcell[level], h->n_pcell[level], h->d_pface[level], h->n_pface[level],
-                               h->d_desc, dstate<double>(U), phys(h), s);
-    } else {
-      launch_copy<float>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<float>(U), s);
-      if (mode == AMR_FILL_FULL && level > 0)
-        launch_prolong<float>(h->ndim, h->d_pcell[level], h->n_pcell[level], h->d_pface[level], h->n_pface[level],
-                              h->d_desc, dstate<float>(U), phys(h), s);
-    }
-    HIPCHK(hipGetLastError());
+    if (h->esize == 8)
+      do_fill<double>(h, level, mode, U_level, U_parent, s);
+    else
+      do_fill<float>(h, level, mode, U_level, U_parent, s);
     return AMR_OK;
   } catch (const std::exception& e) {
     return fail(e);
@@ -775,35 +1164,50 @@ amr_status amr_fill_ghosts_prolong(amr_hierarchy* h, int32_t level, int32_t mode
 }
 
 amr_status amr_advance_patches(amr_hierarchy* h, int32_t cycle, const int32_t* grid_subset, int32_t nsubset,
-                               int32_t band, const amr_state* U_in, amr_state* U_out, const double* dt0,
-                               void* workspace, void* stream) {
+                               int32_t band, const amr_state* U_a, const amr_state* U_b, uint32_t parity,
+                               const double* dt0, void* workspace, void* stream) {
   try {
-    if (!h || !U_in || !U_out || !dt0 || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (!h || !U_a || !U_b || !dt0 || !workspace) throw Error(AMR_EINVAL, "null argument");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<const LaunchList*> lists;
+    const bool f64 = h->esize == 8;
+    auto run = [&](const LaunchList& L) {
+      if (f64)
+        run_list<double>(h, L, U_a, U_b, parity, dt0, workspace, s);
+      else
+        run_list<float>(h, L, U_a, U_b, parity, dt0, workspace, s);
+    };
+    auto regs = [&](int l, int k) {
+      if (f64)
+        write_registers<double>(h, l, k, dt0, workspace, s);
+      else
+        write_registers<float>(h, l, k, dt0, workspace, s);
+    };
     if (cycle >= 0) {
       if (band > 0) {
         if (h->nlev != 1) throw Error(AMR_EINVAL, "an explicit band with a batched cycle needs a single level");
         auto it = h->level0_band_lists.find(band);
         if (it == h->level0_band_lists.end()) throw Error(AMR_EINVAL, "band must be in [2, ghost]");
-        lists.push_back(&it->second);
+        run(it->second);
       } else {
         if (cycle >= (int)h->cycle_lists.size()) throw Error(AMR_EINVAL, "cycle out of range");
-        lists.push_back(&h->cycle_lists[cycle]);
+        run(h->cycle_lists[cycle]);
+        const int L = h->nlev;
+        for (int l = 0; l < L; ++l) {
+          const int span = ipow(h->R, L - 1 - l);
+          if (cycle % span == 0) regs(l, cycle / span);
+        }
       }
     } else {
       if (!grid_subset || nsubset <= 0) throw Error(AMR_EINVAL, "per-grid path needs a grid list");
+      std::vector<int> levels;
       for (int i = 0; i < nsubset; ++i) {
         auto it = h->grid_lists.find({grid_subset[i], band});
         if (it == h->grid_lists.end()) throw Error(AMR_EINVAL, "bad grid id or band for the per-grid path");
-        lists.push_back(&it->second);
+        run(it->second);
+        const int l = h->desc[grid_subset[i]].level;
+        if (std::find(levels.begin(), levels.end(), l) == levels.end()) levels.push_back(l);
       }
-    }
-    for (const LaunchList* L : lists) {
-      if (h->esize == 8)
-        run_list<double>(h, *L, U_in, U_out, dt0, workspace, s);
-      else
-        run_list<float>(h, *L, U_in, U_out, dt0, workspace, s);
+      for (int l : levels) regs(l, l == 0 ? 0 : (h->g - band) / 2);
     }
     return AMR_OK;
   } catch (const std::exception& e) {
@@ -813,9 +1217,36 @@ amr_status amr_advance_patches(amr_hierarchy* h, int32_t cycle, const int32_t* g
 
 amr_status amr_restrict_fluxfix(amr_hierarchy* h, int32_t fine_level, const amr_state* U_fine, amr_state* U_coarse,
                                 void* workspace, void* stream) {
-  (void)h; (void)fine_level; (void)U_fine; (void)U_coarse; (void)workspace; (void)stream;
-  g_last_error = "amr_restrict_fluxfix: not built yet";
-  return AMR_EUNSUPPORTED;
+  try {
+    if (!h || !U_fine || !U_coarse || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (fine_level < 1 || fine_level >= h->nlev) throw Error(AMR_EINVAL, "fine_level must be in [1, nlevels)");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->esize == 8)
+      do_sync<double>(h, fine_level, U_fine, U_coarse, workspace, s);
+    else
+      do_sync<float>(h, fine_level, U_fine, U_coarse, workspace, s);
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_coarse_step(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t* parity, double* dt0,
+                           void* workspace, int32_t mode, void* stream) {
+  try {
+    if (!h || !U_a || !U_b || !parity || !dt0 || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (mode != 0 && mode != 1) throw Error(AMR_EINVAL, "mode must be 0 (batched) or 1 (per-grid)");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t par = *parity;
+    if (h->esize == 8)
+      coarse_step<double>(h, U_a, U_b, par, dt0, workspace, mode, s);
+    else
+      coarse_step<float>(h, U_a, U_b, par, dt0, workspace, mode, s);
+    *parity = par;
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
 }
 
 amr_status amr_advance_adjoint(amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, const double* dts,

@@ -1,0 +1,188 @@
+// Level synchronisation kernels for gfx950: coarse/fine registers, reflux,
+// EMF correction and restriction (the (S)ynchronise and (R)estrict steps of
+// the paper's level cycle, Sec. 4).  Every kernel is a gather over tables
+// built by the host runtime: one thread per register, cell or face copy, so
+// each output has exactly one writer and no atomics are used.
+#include "amr_internal.hpp"
+#include "emf.hpp"
+#include "sync_internal.hpp"
+
+namespace amr {
+
+namespace {
+
+inline int blocks_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65535) b = 65535;
+  return (int)(b < 1 ? 1 : b);
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_reg_faces(const FaceRegEntry* __restrict__ ent, int n, DevFlux<T> F,
+                                                   T* __restrict__ reg, int nreg, int slot,
+                                                   const double* __restrict__ dt0p, double dt_div) {
+  const T dt = T(dt0p[0] / dt_div);
+  const int ns = NDIM == 2 ? 6 : 5;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const FaceRegEntry e = ent[t];
+    T* out = reg + ((int64_t)slot * nreg + e.reg) * 6;
+    for (int q = 0; q < ns; ++q) {
+      const int s = q < 5 ? q : 7;
+      const T* f = F.f[e.d][flux_comp(s, e.d)];
+      T m = T(0);
+      for (int i = 0; i < e.n; ++i) m += f[e.e[i]];
+      out[q] = dt * (m / T(e.n));
+    }
+  }
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_reg_edges(const EdgeRegEntry* __restrict__ ent, int n,
+                                                   const GridDesc* __restrict__ grids, DevFlux<T> F,
+                                                   T* __restrict__ reg, int nreg, int slot,
+                                                   const double* __restrict__ dt0p, double dt_div) {
+  const T dt = T(dt0p[0] / dt_div);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const EdgeRegEntry e = ent[t];
+    const GridDesc G = grids[e.grid];
+    const int64_t st[3] = {1, G.P[0], NDIM == 3 ? (int64_t)G.P[0] * G.P[1] : 0};
+    T m = T(0);
+    for (int i = 0; i < e.n; ++i) {
+      T v;
+      if (e.a == 0) v = edge_emf<0>(F, e.e[i], st);
+      else if (e.a == 1) v = edge_emf<1>(F, e.e[i], st);
+      else v = edge_emf<2>(F, e.e[i], st);
+      m += v;
+    }
+    reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
+  }
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_reflux(const RefluxEntry* __restrict__ ent, int n, const T* __restrict__ reg,
+                                                int nreg, int R, DevState<T> U) {
+  const int ns = NDIM == 2 ? 6 : 5;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const RefluxEntry e = ent[t];
+    for (int q = 0; q < ns; ++q) {
+      const int s = q < 5 ? q : 7;
+      T acc = U.f[s][e.cell];
+      for (int i = 0; i < e.n; ++i) {
+        const T* r = reg + (int64_t)e.reg[i] * 6 + q;
+        T fine = T(0);
+        for (int k = 1; k <= R; ++k) fine += r[(int64_t)k * nreg * 6];
+        const T delta = r[0] - fine;
+        acc += T(e.coef[i]) * delta;
+      }
+      U.f[s][e.cell] = acc;
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_emffix(const EmfFixEntry* __restrict__ ent, int n, const T* __restrict__ reg,
+                                                int nreg, int R, DevState<T> U) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const EmfFixEntry e = ent[t];
+    T corr = T(0);
+    for (int i = 0; i < e.n; ++i) {
+      const T* r = reg + e.reg[i];
+      T fine = T(0);
+      for (int k = 1; k <= R; ++k) fine += r[(int64_t)k * nreg];
+      corr += T(e.coef[i]) * (fine - r[0]);
+    }
+    U.f[5 + e.d][e.face] -= corr;
+  }
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_restrict(const RestrictEntry* __restrict__ ent, int n,
+                                                  const GridDesc* __restrict__ grids, int R, DevState<T> Uf,
+                                                  DevState<T> Uc) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const RestrictEntry e = ent[t];
+    const GridDesc G = grids[e.fgrid];
+    const int64_t st[3] = {1, G.P[0], (int64_t)G.P[0] * G.P[1]};
+    if (e.d < 0) {
+      const int ns = NDIM == 2 ? 6 : 5;
+      const int nz = NDIM == 3 ? R : 1;
+      for (int q = 0; q < ns; ++q) {
+        const int s = q < 5 ? q : 7;
+        T m = T(0);
+        for (int kz = 0; kz < nz; ++kz)
+          for (int ky = 0; ky < R; ++ky)
+            for (int kx = 0; kx < R; ++kx) m += Uf.f[s][e.src + kx + ky * st[1] + kz * st[2]];
+        Uc.f[s][e.dst] = m / T(R * R * nz);
+      }
+    } else {
+      const int d = e.d;
+      const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+      const int n1 = a1 < NDIM ? R : 1, n2 = a2 < NDIM ? R : 1;
+      T m = T(0);
+      for (int i1 = 0; i1 < n1; ++i1)
+        for (int i2 = 0; i2 < n2; ++i2) m += Uf.f[5 + d][e.src + i1 * st[a1] + i2 * st[a2]];
+      Uc.f[5 + d][e.dst] = m / T(n1 * n2);
+    }
+  }
+}
+
+}  // namespace
+
+template <class T>
+void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
+                      DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
+                      double dt_div, hipStream_t s) {
+  if (nf > 0) {
+    if (ndim == 3)
+      hipLaunchKernelGGL((k_reg_faces<T, 3>), dim3(blocks_for(nf)), dim3(256), 0, s, fe, nf, F, freg, nfreg, slot, dt0,
+                         dt_div);
+    else
+      hipLaunchKernelGGL((k_reg_faces<T, 2>), dim3(blocks_for(nf)), dim3(256), 0, s, fe, nf, F, freg, nfreg, slot, dt0,
+                         dt_div);
+  }
+  if (ne > 0) {
+    if (ndim == 3)
+      hipLaunchKernelGGL((k_reg_edges<T, 3>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg,
+                         slot, dt0, dt_div);
+    else
+      hipLaunchKernelGGL((k_reg_edges<T, 2>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg,
+                         slot, dt0, dt_div);
+  }
+}
+
+template <class T>
+void launch_sync(int ndim, int R, const GridDesc* grids, const SyncTables& t, const T* freg, const T* ereg,
+                 DevState<T> Uf, DevState<T> Uc, hipStream_t s) {
+  if (t.n_reflux > 0) {
+    if (ndim == 3)
+      hipLaunchKernelGGL((k_reflux<T, 3>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
+                         t.nfreg, R, Uc);
+    else
+      hipLaunchKernelGGL((k_reflux<T, 2>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
+                         t.nfreg, R, Uc);
+  }
+  if (t.n_emffix > 0)
+    hipLaunchKernelGGL((k_emffix<T>), dim3(blocks_for(t.n_emffix)), dim3(256), 0, s, t.d_emffix, t.n_emffix, ereg,
+                       t.nereg, R, Uc);
+  if (t.n_restrict > 0) {
+    if (ndim == 3)
+      hipLaunchKernelGGL((k_restrict<T, 3>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
+                         t.n_restrict, grids, R, Uf, Uc);
+    else
+      hipLaunchKernelGGL((k_restrict<T, 2>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
+                         t.n_restrict, grids, R, Uf, Uc);
+  }
+}
+
+template void launch_registers<float>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
+                                      DevFlux<float>, float*, float*, int, int, int, const double*, double,
+                                      hipStream_t);
+template void launch_registers<double>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
+                                       DevFlux<double>, double*, double*, int, int, int, const double*, double,
+                                       hipStream_t);
+template void launch_sync<float>(int, int, const GridDesc*, const SyncTables&, const float*, const float*,
+                                 DevState<float>, DevState<float>, hipStream_t);
+template void launch_sync<double>(int, int, const GridDesc*, const SyncTables&, const double*, const double*,
+                                  DevState<double>, DevState<double>, hipStream_t);
+
+}  // namespace amr

@@ -70,3 +70,28 @@ def test_create_rejects_misaligned_and_unnested_fine_grids():
 def test_strerror_names_every_status():
     for s in (0, -1, -2, -3, -4, -5):
         assert A.lib().amr_strerror(s).decode() != "unknown status"
+
+
+def test_validate_builds_tables_on_host():
+    """amr_validate runs every check and table build of amr_create without a
+    device, including the bounds check of every table element."""
+    from paper_1110_1616_amd import inputs as I
+    grids = I.amr_hierarchy(3, (24, 24, 24), 3, seed=11, ext=(8, 16))
+    p = A.make_params(3, (24, 24, 24), nlevels=3, ghost=4)
+    st = A.amr_validate(p, A.make_grids(grids))
+    assert st["grids"] == len(grids) and st["sync_entries"] > 0 and st["prolong_entries"] > 0
+    grids2 = I.amr_hierarchy(2, (32, 32), 3, seed=4, ext=(8, 16))
+    st2 = A.amr_validate(A.make_params(2, (32, 32), nlevels=3, ghost=4), A.make_grids(grids2))
+    assert st2["grids"] == len(grids2)
+
+
+def test_validate_rejects_broken_nesting():
+    p = A.make_params(3, (16, 16, 16), nlevels=2, ghost=4)
+    # a fine grid whose grown box (3 coarse cells) leaves the level-0 grid
+    grids = [(0, (0, 0, 0), (8, 16, 16)), (1, (4, 4, 4), (12, 12, 12))]
+    with pytest.raises(A.AmrError):
+        A.amr_validate(p, A.make_grids(grids))
+    # band narrower than 2R
+    p2 = A.make_params(3, (16, 16, 16), nlevels=2, ghost=2)
+    with pytest.raises(A.AmrError):
+        A.amr_validate(p2, A.make_grids([(0, (0, 0, 0), (16, 16, 16)), (1, (8, 8, 8), (16, 16, 16))]))
