@@ -216,6 +216,16 @@ amr_status amr_restrict_fluxfix(amr_hierarchy* h, int32_t fine_level, const amr_
 amr_status amr_coarse_step(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t* parity, double* dt0,
                            void* workspace, int32_t mode, void* stream);
 
+/* Capture amr_coarse_step (same arguments, on the non-default `stream`) into
+ * HIP graphs: one starting from `parity` and, because level 0 changes buffer
+ * every coarse step, one starting from the parity after it.  The graphs bake
+ * in the state pointers, dt0 and workspace.  amr_graph_launch() replays the
+ * graph that starts from *parity and updates it.  A new capture replaces the
+ * old graphs. */
+amr_status amr_graph_capture(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t parity, double* dt0,
+                             void* workspace, int32_t mode, void* stream);
+amr_status amr_graph_launch(amr_hierarchy* h, uint32_t* parity, void* stream);
+
 /* Discrete adjoint of nsteps single-level steps of one grid or all grids of
  * one level (limiter and Riemann branches frozen from the recomputed forward
  * pass; constrained transport and the periodic ghost fill included).

@@ -76,6 +76,9 @@ def lib():
         L.amr_advance_adjoint.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
                                           C.POINTER(amr_state), _VP, _VP]
         L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
+        L.amr_graph_capture.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP,
+                                        C.c_int32, _VP]
+        L.amr_graph_launch.argtypes = [_VP, C.POINTER(C.c_uint32), _VP]
         L.amr_set_kernel_timing.argtypes = [_VP, C.c_int32]
         L.amr_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         _LIB = L
@@ -214,6 +217,17 @@ def amr_get_error_flags(h):
     return fl.value, bad.value
 
 
+def amr_graph_capture(h, Ua, Ub, parity, dt0, ws, mode=0):
+    _check(lib().amr_graph_capture(h, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws), mode, _stream()),
+           "amr_graph_capture")
+
+
+def amr_graph_launch(h, parity):
+    par = C.c_uint32(parity)
+    _check(lib().amr_graph_launch(h, C.byref(par), _stream()), "amr_graph_launch")
+    return par.value
+
+
 def amr_set_kernel_timing(h, enable):
     _check(lib().amr_set_kernel_timing(h, int(bool(enable))), "amr_set_kernel_timing")
 
@@ -314,6 +328,12 @@ class Hierarchy:
 
     def coarse_step(self, Ua, Ub, parity, mode=0):
         return amr_coarse_step(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, mode)
+
+    def graph_capture(self, Ua, Ub, parity, mode=0):
+        amr_graph_capture(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, mode)
+
+    def graph_launch(self, parity):
+        return amr_graph_launch(self.h, parity)
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua

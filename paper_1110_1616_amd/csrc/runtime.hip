@@ -106,6 +106,11 @@ struct amr_hierarchy {
   std::map<int, LaunchList> level0_band_lists;          // band -> all level-0 grids
   int zchunk = 16;
 
+  // captured coarse steps: graph[p] starts from level-0 parity bit p
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  uint32_t graph_parity[2] = {0, 0};
+  bool capturing = false;
+
   // optional per-kernel timing with HIP events on the launch stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -121,6 +126,8 @@ struct amr_hierarchy {
   }
 
   ~amr_hierarchy() {
+    for (auto g : graph_exec)
+      if (g) (void)hipGraphExecDestroy(g);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     (void)hipFree(d_desc);
     (void)hipFree(d_fitems);
@@ -834,7 +841,8 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
   DevFlux<T> F = dflux<T>(h, ws);
   Phys ph = phys(h);
   int e0 = 0, e1 = 0, e2 = 0;
-  if (h->timing) {
+  const bool timing = h->timing && !h->capturing;
+  if (timing) {
     e0 = h->take_event();
     e1 = h->take_event();
     e2 = h->take_event();
@@ -842,10 +850,10 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
   }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err, s);
   HIPCHK(hipGetLastError());
-  if (h->timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
+  if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
   launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, s);
   HIPCHK(hipGetLastError());
-  if (h->timing) {
+  if (timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
     h->ev_pairs[0].push_back({e0, e1});
     h->ev_pairs[1].push_back({e1, e2});
@@ -1243,6 +1251,69 @@ amr_status amr_coarse_step(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uin
     else
       coarse_step<float>(h, U_a, U_b, par, dt0, workspace, mode, s);
     *parity = par;
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_graph_capture(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t parity, double* dt0,
+                             void* workspace, int32_t mode, void* stream) {
+  try {
+    if (!h || !U_a || !U_b || !dt0 || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (!stream) throw Error(AMR_EINVAL, "graph capture needs a non-default stream");
+    if (mode != 0 && mode != 1) throw Error(AMR_EINVAL, "mode must be 0 (batched) or 1 (per-grid)");
+    hipStream_t s = (hipStream_t)stream;
+    for (auto& g : h->graph_exec)
+      if (g) {
+        HIPCHK(hipGraphExecDestroy(g));
+        g = nullptr;
+      }
+    uint32_t par = parity;
+    for (int k = 0; k < 2; ++k) {
+      const uint32_t start = par;
+      h->capturing = true;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        if (h->esize == 8)
+          coarse_step<double>(h, U_a, U_b, par, dt0, workspace, mode, s);
+        else
+          coarse_step<float>(h, U_a, U_b, par, dt0, workspace, mode, s);
+      } catch (...) {
+        hipGraph_t gdrop;
+        (void)hipStreamEndCapture(s, &gdrop);
+        if (gdrop) (void)hipGraphDestroy(gdrop);
+        h->capturing = false;
+        throw;
+      }
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamEndCapture(s, &graph));
+      h->capturing = false;
+      hipGraphExec_t ex = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(ie);
+      const int slot = start & 1u;
+      h->graph_exec[slot] = ex;
+      h->graph_parity[slot] = start;
+      if (par == start) break;  // every level returns to its buffer: one graph suffices
+    }
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    h->capturing = false;
+    return fail(e);
+  }
+}
+
+amr_status amr_graph_launch(amr_hierarchy* h, uint32_t* parity, void* stream) {
+  try {
+    if (!h || !parity) throw Error(AMR_EINVAL, "null argument");
+    const int slot = *parity & 1u;
+    if (!h->graph_exec[slot] || h->graph_parity[slot] != *parity)
+      throw Error(AMR_EINVAL, "no captured coarse step starts from this parity");
+    HIPCHK(hipGraphLaunch(h->graph_exec[slot], (hipStream_t)stream));
+    // level 0 steps once per coarse step; level l > 0 steps R^l (even) times
+    *parity ^= (h->R % 2 == 0) ? 1u : ((1u << h->nlev) - 1u);
     return AMR_OK;
   } catch (const std::exception& e) {
     return fail(e);
