@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["oracle_capi.cpp", "amr_oracle.cpp"]
+SOURCES = ["oracle_capi.cpp", "amr_oracle.cpp", "adjoint_oracle.cpp"]
 HEADERS = ["scheme.hpp"]
 
 

@@ -302,3 +302,70 @@ def amr_level_order(nlev):
     buf = (C.c_int * 4096)()
     n = lib().orc_amr_level_order(C.c_int(nlev), buf, 4096)
     return list(buf[:n])
+
+
+# ------------------------------------------------------------ derivatives
+def _ke_args(ic, box_lo, box_len):
+    ndim, n = ic["ndim"], ic["n"]
+    k1, pp = _ptrs(ic["prim"])
+    k2, pb = _ptrs(ic["b"])
+    lo = (C.c_int * 3)(*(list(box_lo) + [0] * (3 - len(box_lo))))
+    ln = (C.c_int * 3)(*(list(box_len) + [1] * (3 - len(box_len))))
+    return ndim, n, (k1, k2), pp, pb, lo, ln
+
+
+def ke_loss(ic, gamma, dts, box_lo, box_len):
+    """Kinetic energy of box S after len(dts) frozen-dt steps (band 2 refilled
+    every step, periodic)."""
+    ndim, n, keep, pp, pb, lo, ln = _ke_args(ic, box_lo, box_len)
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    J = C.c_double()
+    rc = lib().orc_ke_loss(C.c_int(ndim), _ivec(n), C.c_double(gamma), C.c_int(len(d)), d.ctypes.data_as(_dp), pp,
+                           pb, lo, ln, C.byref(J))
+    if rc != 0:
+        raise RuntimeError("oracle ke_loss failed")
+    return J.value
+
+
+def ke_tlm(ic, gamma, dts, box_lo, box_len, direction):
+    """(J, dJ) along direction = [drho, dvx, dvy, dvz] by forward mode."""
+    ndim, n, keep, pp, pb, lo, ln = _ke_args(ic, box_lo, box_len)
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    k3, pd = _ptrs(direction)
+    J, dJ = C.c_double(), C.c_double()
+    rc = lib().orc_ke_tlm(C.c_int(ndim), _ivec(n), C.c_double(gamma), C.c_int(len(d)), d.ctypes.data_as(_dp), pp, pb,
+                          lo, ln, pd, C.byref(J), C.byref(dJ))
+    if rc != 0:
+        raise RuntimeError("oracle ke_tlm failed")
+    return J.value, dJ.value
+
+
+def ke_grad(ic, gamma, dts, box_lo, box_len):
+    """(J, [dJ/drho, dJ/dvx, dJ/dvy, dJ/dvz]) by reverse mode (tape)."""
+    ndim, n, keep, pp, pb, lo, ln = _ke_args(ic, box_lo, box_len)
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    outs = [np.zeros_like(np.asarray(ic["prim"][0], dtype=np.float64)) for _ in range(4)]
+    k3, po = _ptrs(outs)
+    J = C.c_double()
+    L = lib()
+    L.orc_adj_last_error.restype = C.c_char_p
+    rc = L.orc_ke_grad(C.c_int(ndim), _ivec(n), C.c_double(gamma), C.c_int(len(d)), d.ctypes.data_as(_dp), pp, pb, lo,
+                       ln, po, C.byref(J))
+    if rc != 0:
+        raise RuntimeError("oracle ke_grad: " + L.orc_adj_last_error().decode())
+    return J.value, k3
+
+
+def ke_branch_signature(ic, gamma, dts):
+    """Hash of every branch decision of the forward run (equal hashes: the
+    same branches were taken everywhere)."""
+    ndim, n = ic["ndim"], ic["n"]
+    k1, pp = _ptrs(ic["prim"])
+    k2, pb = _ptrs(ic["b"])
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    sig = C.c_uint64()
+    rc = lib().orc_ke_branch_signature(C.c_int(ndim), _ivec(n), C.c_double(gamma), C.c_int(len(d)),
+                                       d.ctypes.data_as(_dp), pp, pb, C.byref(sig))
+    if rc != 0:
+        raise RuntimeError("oracle ke_branch_signature failed")
+    return sig.value

@@ -38,13 +38,44 @@ template <class T> struct StepMark {
   static void mark(int) {}
 };
 
+// Branch log: when enabled, every data-dependent decision of the scheme
+// (minmod choice, min/max, sign, clamp, HLLD region and degeneracy) is folded
+// into a running FNV-1a hash in evaluation order, so two runs that took the
+// same branches everywhere have the same signature.  Used to tell apart
+// finite-difference directions that cross a kink of the piecewise-smooth map.
+struct BranchLog {
+  static bool& on() {
+    static bool v = false;
+    return v;
+  }
+  static uint64_t& hash() {
+    static uint64_t h = 1469598103934665603ull;
+    return h;
+  }
+  static void note(int choice) {
+    if (!on()) return;
+    uint64_t& h = hash();
+    h ^= (uint64_t)(choice + 1);
+    h *= 1099511628211ull;
+  }
+};
+
 // ---------------------------------------------------------------- scalar glue
 inline double value(double x) { return x; }
 inline double Sqrt(double x) { return std::sqrt(x); }
 
-template <class T> inline T Abs(const T& x) { return value(x) < 0.0 ? -x : x; }
-template <class T> inline T Min(const T& a, const T& b) { return value(b) < value(a) ? b : a; }
-template <class T> inline T Max(const T& a, const T& b) { return value(b) > value(a) ? b : a; }
+template <class T> inline T Abs(const T& x) {
+  BranchLog::note(value(x) < 0.0);
+  return value(x) < 0.0 ? -x : x;
+}
+template <class T> inline T Min(const T& a, const T& b) {
+  BranchLog::note(value(b) < value(a));
+  return value(b) < value(a) ? b : a;
+}
+template <class T> inline T Max(const T& a, const T& b) {
+  BranchLog::note(value(b) > value(a));
+  return value(b) > value(a) ? b : a;
+}
 
 // Primitive slots (lab frame) and conserved slots share indices 0..7:
 //   W = (rho, vx, vy, vz, p, Bx, By, Bz),  U = (rho, mx, my, mz, E, Bx, By, Bz).
@@ -54,8 +85,13 @@ enum { NVAR = 8 };
 // minmod(a, b): zero if a*b <= 0, else the argument of smaller magnitude
 // (slope limiter of the MUSCL reconstruction).  On |a| == |b| it returns a.
 template <class T> inline T minmod(const T& a, const T& b) {
-  if (value(a) * value(b) <= 0.0) return T(0.0);
-  return (std::fabs(value(b)) < std::fabs(value(a))) ? b : a;
+  if (value(a) * value(b) <= 0.0) {
+    BranchLog::note(0);
+    return T(0.0);
+  }
+  const bool pick_b = std::fabs(value(b)) < std::fabs(value(a));
+  BranchLog::note(pick_b ? 2 : 1);
+  return pick_b ? b : a;
 }
 
 // Conserved from primitive: m = rho v, E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2
@@ -111,6 +147,7 @@ template <class T> inline void phys_flux(const T* W, int d, double gamma, T* F) 
 template <class T> inline T fast_speed(const T& rho, const T& p, const T& B2, const T& Bn, double gamma) {
   T a = (gamma * p + B2) / rho;
   T disc = a * a - 4.0 * gamma * p * Bn * Bn / (rho * rho);
+  BranchLog::note(value(disc) < 0.0);
   if (value(disc) < 0.0) disc = T(0.0);
   return Sqrt(0.5 * (a + Sqrt(disc)));
 }
@@ -169,6 +206,7 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
   pflux(rR, uR, vR, wR, ptR, ER, byR, bzR, FR);
 
   HlldInfo inf;
+  BranchLog::note(10 + (value(SL) > 0.0));
   if (value(SL) > 0.0) {  // whole fan moves right: upwind flux is F_L
     for (int c = 0; c < 7; ++c) F[c] = FL[c];
     inf.region = 0;
@@ -191,6 +229,7 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
     s.r = r * dS / dSM;
     T D = r * dS * dSM - Bn * Bn;
     degen = std::fabs(value(D)) <= 1e-12 * value(pts);
+    BranchLog::note(20 + degen);
     if (degen) {
       s.v = v; s.w = w; s.by = by; s.bz = bz;
     } else {
@@ -236,6 +275,8 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
 
   // Region cascade (first true test wins): S*_L >= 0 -> F*_L; S_M >= 0 -> F**_L;
   // S*_R >= 0 -> F**_R; S_R >= 0 -> F*_R; otherwise F_R.
+  BranchLog::note(30 + (value(SLs) >= 0.0) + 2 * (value(SM) >= 0.0) + 4 * (value(SRs) >= 0.0) +
+                  8 * (value(SR) >= 0.0));
   if (value(SLs) >= 0.0) {
     for (int c = 0; c < 7; ++c) F[c] = FsL[c];
     inf.region = 1;
@@ -257,6 +298,7 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
   // Inner (double-star) states.
   T UssL[7], UssR[7];
   bool dd = 0.5 * value(Bn) * value(Bn) <= 1e-12 * value(pts);
+  BranchLog::note(50 + dd);
   inf.degen_dstar = dd;
   if (dd) {
     for (int c = 0; c < 7; ++c) { UssL[c] = UsL[c]; UssR[c] = UsR[c]; }
@@ -379,7 +421,7 @@ void step(const State<T>& in, State<T>& out, int gv, T dt, const StepParams& P, 
   const int nd = L.ndim;
   const double gamma = P.gamma;
   if (gv < 2 || gv > L.g) throw std::runtime_error("step: band too narrow");
-  const bool OMP_OK = OmpSafe<T>::value;
+  const bool OMP_OK = OmpSafe<T>::value && !BranchLog::on();
   (void)OMP_OK;
   out = in;
 

@@ -1,0 +1,106 @@
+"""Pins of the oracle's derivatives of the advance (CPU only): the reverse
+mode (tape) and the forward mode (dual numbers) agree to rounding (the
+dot-product test), and both agree with centred finite differences of the
+plain forward run on smooth data."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1110_1616_amd import inputs as I
+
+GAMMA = 5.0 / 3.0
+
+
+def _case(ndim):
+    if ndim == 3:
+        ic = I.smooth_mhd(3, (12, 12, 12), seed=4, v_rms=0.1, b_rms=0.3)
+        box = ((7, 2, 9), (6, 6, 6))  # wraps around the periodic edge
+        nsteps = 4
+    else:
+        ic = I.smooth_mhd(2, (24, 24), seed=4, v_rms=0.1, b_rms=0.3)
+        box = ((17, 3), (12, 12))
+        nsteps = 6
+    _, dts = O.uniform_run(ic, GAMMA, 0.4, nsteps, g=2)
+    return ic, dts, box
+
+
+def _directions(ic, k, seed=444):
+    rng = np.random.default_rng(seed)
+    shp = np.asarray(ic["prim"][0]).shape
+    return [[0.1 * rng.normal(size=shp) for _ in range(4)] for _ in range(k)]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_adjoint_tlm_dot_product(ndim):
+    ic, dts, (lo, ln) = _case(ndim)
+    J, g = O.ke_grad(ic, GAMMA, dts, lo, ln)
+    for d in _directions(ic, 3):
+        J2, dJ = O.ke_tlm(ic, GAMMA, dts, lo, ln, d)
+        assert J2 == pytest.approx(J, rel=1e-14)
+        adj = sum(float(np.sum(gi * di)) for gi, di in zip(g, d))
+        assert abs(adj - dJ) <= 1e-12 * abs(dJ), (adj, dJ)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_tlm_matches_centred_differences(ndim):
+    """Centred differences agree with the tangent-linear derivative to 1e-6
+    relative whenever the +-eps runs take exactly the branches of the
+    unperturbed run.  The map is only piecewise smooth (minmod choices and
+    the min/max wave-speed tests of HLLD have kinks where the left and right
+    states nearly coincide, which in smooth flow happens at some face almost
+    always), so each direction uses eps = 1e-6 if no branch flips there, else
+    eps = 1e-7; a direction that flips at both must still agree to 1e-4."""
+    ic, dts, (lo, ln) = _case(ndim)
+    sig0 = O.ke_branch_signature(ic, GAMMA, dts)
+    smooth = 0
+    for d in _directions(ic, 6, seed=7):
+        _, dJ = O.ke_tlm(ic, GAMMA, dts, lo, ln, d)
+        ok = False
+        for eps in (1e-6, 1e-7):
+            icp = dict(ic)
+            icm = dict(ic)
+            icp["prim"] = [p + eps * dd for p, dd in zip(ic["prim"][:4], d)] + [ic["prim"][4]]
+            icm["prim"] = [p - eps * dd for p, dd in zip(ic["prim"][:4], d)] + [ic["prim"][4]]
+            fd = (O.ke_loss(icp, GAMMA, dts, lo, ln) - O.ke_loss(icm, GAMMA, dts, lo, ln)) / (2 * eps)
+            if O.ke_branch_signature(icp, GAMMA, dts) == sig0 == O.ke_branch_signature(icm, GAMMA, dts):
+                assert abs(fd - dJ) <= 1e-6 * abs(dJ), (eps, fd, dJ)
+                smooth += 1
+                ok = True
+                break
+            assert abs(fd - dJ) <= 1e-4 * abs(dJ), (eps, fd, dJ)
+        if ndim == 2:
+            assert ok  # the 2D case has no kink within +-1e-6 in these directions
+    assert smooth >= 4
+
+
+def test_branch_signature_detects_a_flip():
+    ic, dts, _ = _case(2)
+    s0 = O.ke_branch_signature(ic, GAMMA, dts)
+    assert O.ke_branch_signature(ic, GAMMA, dts) == s0
+    big = dict(ic)
+    big["prim"] = [p.copy() for p in ic["prim"]]
+    big["prim"][0][0, 5, 5] += 0.2  # a large bump changes slopes around it
+    assert O.ke_branch_signature(big, GAMMA, dts) != s0
+
+
+def test_gradient_is_local_to_the_dependency_cone():
+    """After n steps a control influences the loss only through cells within
+    2n cells of the box (two cells of stencil per step)."""
+    ic, dts, (lo, ln) = _case(3)
+    _, g = O.ke_grad(ic, GAMMA, dts, lo, ln)
+    n = 12
+    reach = 2 * len(dts)
+    far = np.ones((n, n, n), dtype=bool)
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                dist = []
+                for a, x in enumerate((i, j, k)):
+                    dd = min((x - (lo[a] + t)) % n for t in range(ln[a]))
+                    dd = min(dd, min(((lo[a] + t) - x) % n for t in range(ln[a])))
+                    dist.append(dd)
+                if max(dist) <= reach:
+                    far[k, j, i] = False
+    if np.any(far):
+        assert all(np.all(gi[far] == 0.0) for gi in g)
