@@ -226,16 +226,50 @@ amr_status amr_graph_capture(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, u
                              void* workspace, int32_t mode, void* stream);
 amr_status amr_graph_launch(amr_hierarchy* h, uint32_t* parity, void* stream);
 
-/* Discrete adjoint of nsteps single-level steps of one grid or all grids of
- * one level (limiter and Riemann branches frozen from the recomputed forward
- * pass; constrained transport and the periodic ghost fill included).
- * grid_or_level >= 0: that grid; < 0: every grid of level -(v+1).  dts: host
- * array of the nsteps frozen step sizes.  U_checkpoint: state at the first
- * step.  lambda_inout: on entry the adjoint at the last step, on exit at the
- * first.  Forward states of the segment are recomputed into workspace. */
+/* Discrete adjoint of nsteps single-level steps (reverse mode of the
+ * advance above with the limiter, wave-speed and HLLD region choices frozen
+ * at the recomputed forward values; constrained transport and the
+ * same-level ghost copy included).  The differentiated map is, per step:
+ * refresh the band by the same-level copy (AMR_FILL_SAME_LEVEL), then one
+ * band-2 step of every grid of the level with the level-0 step size dts[k]
+ * (level l steps by dts[k] / R^l).  Band elements the same-level copy does
+ * not fill (prolonged ones, levels > 0) keep U_checkpoint's values through
+ * the segment and are constants of the map.
+ *   grid_or_level >= 0: that grid, which must be the only grid of its level
+ *     (AMR_EUNSUPPORTED otherwise); < 0: every grid of level -(v+1).
+ *   dts: host array of the nsteps frozen step sizes (> 0).
+ *   U_checkpoint: the state before the first step (read only; only the
+ *     selected level is used).
+ *   lambda_inout: pools laid out like a state.  On entry, the adjoint of the
+ *     state after the last step on the level's own elements (cells [0, n),
+ *     faces [0, n] along their normal and [0, n) across); band entries are
+ *     ignored.  On exit, the adjoint of the state before the first step: own
+ *     elements hold it (band images folded into the elements they copy),
+ *     band elements are zero; elements of other levels are untouched.
+ *   workspace: device memory of amr_adjoint_workspace() bytes (the forward
+ *     recompute of the segment's states lives there).
+ * The cost is one forward pass (nsteps - 1 steps) plus nsteps reverse steps. */
 amr_status amr_advance_adjoint(amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, const double* dts,
                                const amr_state* U_checkpoint, amr_state* lambda_inout, void* workspace,
                                void* stream);
+
+/* Workspace bytes amr_advance_adjoint() needs for that selection and nsteps. */
+amr_status amr_adjoint_workspace(const amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, int64_t* bytes);
+
+/* Adjoint of amr_store_interior(): lambda's own elements of `grid` <- g, the
+ * eight interior-layout float64 device arrays amr_store_interior() writes
+ * (cells, then x-, y-, z-faces; in 2D g[7] is the cell Bz).  Band elements
+ * are not written. */
+amr_status amr_store_interior_adjoint(amr_hierarchy* h, int32_t grid, const double* const* g, amr_state* lambda,
+                                      void* stream);
+
+/* Adjoint of amr_load_primitive() with respect to the cell density and
+ * velocity (pressure and face B held fixed): grad[0..3] (float64 device
+ * arrays, interior cell layout) <- d/d(rho, vx, vy, vz) given lambda, the
+ * adjoint of the loaded state.  prim[0..3]: the rho, vx, vy, vz arrays
+ * passed to amr_load_primitive(). */
+amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const double* const* prim,
+                                      const amr_state* lambda, double* const* grad, void* stream);
 
 /* Measurement hooks.  With timing enabled, every batched or per-grid
  * advance records HIP events on its stream around its flux and update
@@ -249,6 +283,15 @@ amr_status amr_kernel_times(amr_hierarchy* h, double* flux_ms, double* update_ms
  * non-physical state met.  first_bad_cell: element index of one such cell or
  * -1.  Clears the flags. */
 amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first_bad_cell);
+
+/* Host-only check of the hand-written pointwise adjoints that
+ * amr_advance_adjoint() is built from (no GPU needed).  which: 0 primitive
+ * recovery, 1 conserved from primitive, 2..4 physical flux along x, y, z,
+ * 5 fast magnetosonic speed, 6 HLLD flux.  For ntrials random physical
+ * states drawn from `seed` it returns the largest relative mismatch of the
+ * dot-product test <a, J d> = <J^T a, d>, with J d evaluated exactly by a
+ * forward-mode dual number.  `which` out of range or ntrials < 1 returns -1. */
+double amr_selfcheck_adjoint(int32_t which, int32_t ntrials, uint64_t seed);
 
 /* Text of the last error on this host thread. */
 const char* amr_last_error(void);

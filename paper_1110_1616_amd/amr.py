@@ -75,6 +75,9 @@ def lib():
         L.amr_restrict_fluxfix.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP]
         L.amr_advance_adjoint.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
                                           C.POINTER(amr_state), _VP, _VP]
+        L.amr_adjoint_workspace.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+        L.amr_store_interior_adjoint.argtypes = [_VP, C.c_int32, _PP, C.POINTER(amr_state), _VP]
+        L.amr_load_primitive_adjoint.argtypes = [_VP, C.c_int32, _PP, C.POINTER(amr_state), _PP, _VP]
         L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
         L.amr_graph_capture.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP,
                                         C.c_int32, _VP]
@@ -206,6 +209,23 @@ def amr_advance_adjoint(h, grid_or_level, dts, Uck, lam, ws):
     d = (C.c_double * len(dts))(*[float(x) for x in dts])
     _check(lib().amr_advance_adjoint(h, grid_or_level, len(dts), d, C.byref(Uck), C.byref(lam), _ptr(ws),
                                      _stream()), "amr_advance_adjoint")
+
+
+def amr_adjoint_workspace(h, grid_or_level, nsteps):
+    b = C.c_int64()
+    _check(lib().amr_adjoint_workspace(h, grid_or_level, nsteps, C.byref(b)), "amr_adjoint_workspace")
+    return b.value
+
+
+def amr_store_interior_adjoint(h, grid, g, lam):
+    gg = (C.c_void_p * 8)(*[t.data_ptr() for t in g])
+    _check(lib().amr_store_interior_adjoint(h, grid, gg, C.byref(lam), _stream()), "amr_store_interior_adjoint")
+
+
+def amr_load_primitive_adjoint(h, grid, prim, lam, grad):
+    pp = (C.c_void_p * 4)(*[t.data_ptr() for t in prim[:4]])
+    gg = (C.c_void_p * 4)(*[t.data_ptr() for t in grad])
+    _check(lib().amr_load_primitive_adjoint(h, grid, pp, C.byref(lam), gg, _stream()), "amr_load_primitive_adjoint")
 
 
 def amr_get_error_flags(h):

@@ -1,0 +1,141 @@
+// Per-cell pieces of the forward advance shared by the forward kernels and
+// the adjoint kernels (which re-evaluate them to freeze the same branches).
+#pragma once
+#include "amr_internal.hpp"
+#include "mhd_device.hpp"
+
+namespace amr {
+
+template <int NDIM> struct Idx {
+  int64_t base;  // element of cell (0,0,0)
+  int32_t sy, sz;
+  __device__ __forceinline__ Idx(const GridDesc& G) {
+    sy = G.P[0];
+    sz = G.P[0] * G.P[1];
+    base = G.off + G.g + (int64_t)G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0);
+  }
+  __device__ __forceinline__ int64_t operator()(int i, int j, int k) const {
+    return base + i + (int64_t)j * sy + (NDIM == 3 ? (int64_t)k * sz : 0);
+  }
+};
+
+// Primitive state of cell e (element index) from the conserved state and
+// the bounding faces.
+template <class T, int NDIM>
+__device__ __forceinline__ void load_prim(const DevState<T>& U, int64_t e, int32_t sy, int32_t sz, T gm1, T (&w)[8]) {
+  T u[8];
+  u[0] = U.f[0][e];
+  u[1] = U.f[1][e];
+  u[2] = U.f[2][e];
+  u[3] = U.f[3][e];
+  u[4] = U.f[4][e];
+  u[5] = T(0.5) * (U.f[5][e] + U.f[5][e + 1]);
+  u[6] = T(0.5) * (U.f[6][e] + U.f[6][e + sy]);
+  if (NDIM == 3)
+    u[7] = T(0.5) * (U.f[7][e] + U.f[7][e + sz]);
+  else
+    u[7] = U.f[7][e];
+  to_primitive(u, w, gm1);
+}
+
+__device__ __forceinline__ void flag_bad(ErrBlock* err, int64_t e) {
+  unsigned old = atomicOr(&err->flags, 1u);
+  if ((old & 1u) == 0u) atomicExch((unsigned long long*)&err->first_bad, (unsigned long long)e);
+}
+
+// Direction-d face states of one cell, Hancock-evolved to the half step and
+// returned as rotated primitives (rho, u_n, u_t1, u_t2, p, B_t1, B_t2).
+template <int D, class T>
+__device__ __forceinline__ void rotate7(const T (&w)[8], T (&q)[7]) {
+  q[0] = w[0];
+  q[1] = w[1 + D];
+  q[2] = w[1 + (D + 1) % 3];
+  q[3] = w[1 + (D + 2) % 3];
+  q[4] = w[4];
+  q[5] = w[5 + (D + 1) % 3];
+  q[6] = w[5 + (D + 2) % 3];
+}
+
+template <class T, int NDIM>
+struct Pred {
+  T m[3][7];  // low-side (minus) states per direction
+  T p[3][7];  // high-side (plus) states per direction
+};
+
+// Slopes, face states, Hancock increment and predicted states of one cell.
+// wx/wy/wz hold the neighbours (minus, plus) along each axis; fb[d][0/1] are
+// the cell's low/high face fields along d.
+template <class T, int NDIM>
+__device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8], const T (&wym)[8],
+                                        const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
+                                        const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
+                                        Pred<T, NDIM>& out) {
+  const T gm1 = gam - T(1);
+  const T gm1_inv = T(1) / gm1;
+  T sl[3][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    sl[0][q] = limiter_minmod(w[q] - wxm[q], wxp[q] - w[q]);
+    sl[1][q] = limiter_minmod(w[q] - wym[q], wyp[q] - w[q]);
+    if (NDIM == 3) sl[2][q] = limiter_minmod(w[q] - wzm[q], wzp[q] - w[q]);
+  }
+  T du[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) du[q] = T(0);
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+    T wl[8], wr[8], fl[8], fr[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      wl[q] = w[q] - T(0.5) * sl[d][q];
+      wr[q] = w[q] + T(0.5) * sl[d][q];
+    }
+    wl[5 + d] = fb[d][0];
+    wr[5 + d] = fb[d][1];
+    if (d == 0) {
+      flux_along<0>(wl, fl, gm1_inv);
+      flux_along<0>(wr, fr, gm1_inv);
+    } else if (d == 1) {
+      flux_along<1>(wl, fl, gm1_inv);
+      flux_along<1>(wr, fr, gm1_inv);
+    } else {
+      flux_along<2>(wl, fl, gm1_inv);
+      flux_along<2>(wr, fr, gm1_inv);
+    }
+    const T c = hdt * idx[d];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) du[q] -= c * (fr[q] - fl[q]);
+  }
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      T ws[8], us[8], wb[8];
+      const T h = side ? T(0.5) : T(-0.5);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ws[q] = w[q] + h * sl[d][q];
+      ws[5 + d] = fb[d][side];
+      to_conserved(ws, us, gm1_inv);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) us[q] += du[q];
+      to_primitive(us, wb, gm1);
+      ok = ok && (wb[0] > T(0)) && (wb[4] > T(0));
+      T(&dst)[7] = side ? out.p[d] : out.m[d];
+      if (d == 0) rotate7<0>(wb, dst);
+      else if (d == 1) rotate7<1>(wb, dst);
+      else rotate7<2>(wb, dst);
+    }
+  }
+  return ok;
+}
+
+template <class T>
+__device__ __forceinline__ void hlld7(const T (&l)[7], const T (&r)[7], T bn, T gam, T (&f)[7]) {
+  T ql[8] = {l[0], l[1], l[2], l[3], l[4], bn, l[5], l[6]};
+  T qr[8] = {r[0], r[1], r[2], r[3], r[4], bn, r[5], r[6]};
+  riemann_hlld(ql, qr, bn, gam, f);
+}
+
+
+}  // namespace amr

@@ -15,21 +15,21 @@
 
 namespace amr {
 
-template <class T> __device__ __forceinline__ T dsqrt(T x);
-template <> __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
-template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
+template <class T> __host__ __device__ __forceinline__ T dsqrt(T x);
+template <> __host__ __device__ __forceinline__ double dsqrt<double>(double x) { return __builtin_sqrt(x); }
+template <> __host__ __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_sqrtf(x); }
 
-template <class T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
+template <class T> __host__ __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 
 // minmod limiter: 0 when the one-sided differences disagree in sign (or one
 // is zero), else the one of smaller magnitude (a on ties).
-template <class T> __device__ __forceinline__ T limiter_minmod(T a, T b) {
+template <class T> __host__ __device__ __forceinline__ T limiter_minmod(T a, T b) {
   T r = (dabs(b) < dabs(a)) ? b : a;
   return (a * b > T(0)) ? r : T(0);
 }
 
 // W -> U for one state.
-template <class T> __device__ __forceinline__ void to_conserved(const T (&w)[8], T (&u)[8], T gm1_inv) {
+template <class T> __host__ __device__ __forceinline__ void to_conserved(const T (&w)[8], T (&u)[8], T gm1_inv) {
   u[0] = w[0];
   u[1] = w[0] * w[1];
   u[2] = w[0] * w[2];
@@ -43,7 +43,7 @@ template <class T> __device__ __forceinline__ void to_conserved(const T (&w)[8],
 }
 
 // U -> W for one state.
-template <class T> __device__ __forceinline__ void to_primitive(const T (&u)[8], T (&w)[8], T gm1) {
+template <class T> __host__ __device__ __forceinline__ void to_primitive(const T (&u)[8], T (&w)[8], T gm1) {
   T ir = T(1) / u[0];
   w[0] = u[0];
   w[1] = u[1] * ir;
@@ -59,7 +59,7 @@ template <class T> __device__ __forceinline__ void to_primitive(const T (&u)[8],
 
 // Physical flux along lab axis D of primitive w (8 components, F(B_D) = 0).
 template <int D, class T>
-__device__ __forceinline__ void flux_along(const T (&w)[8], T (&f)[8], T gm1_inv) {
+__host__ __device__ __forceinline__ void flux_along(const T (&w)[8], T (&f)[8], T gm1_inv) {
   const T r = w[0];
   const T vn = w[1 + D];
   const T bn = w[5 + D];
@@ -81,7 +81,7 @@ __device__ __forceinline__ void flux_along(const T (&w)[8], T (&f)[8], T gm1_inv
 
 // Fast magnetosonic speed for density r, pressure p, |B|^2 = b2 and the field
 // component along the direction bn.
-template <class T> __device__ __forceinline__ T fast_magnetosonic(T r, T p, T b2, T bn, T gam) {
+template <class T> __host__ __device__ __forceinline__ T fast_magnetosonic(T r, T p, T b2, T bn, T gam) {
   T ir = T(1) / r;
   T gp = gam * p;
   T a = (gp + b2) * ir;
@@ -97,7 +97,7 @@ template <class T> __device__ __forceinline__ T fast_magnetosonic(T r, T p, T b2
 // contains x/t = 0 is selected at the end (first true test of S_L > 0,
 // S*_L >= 0, S_M >= 0, S*_R >= 0, S_R >= 0; else the right state).
 template <class T>
-__device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T (&qr)[8], T bn, T gam, T (&f)[7]) {
+__host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T (&qr)[8], T bn, T gam, T (&f)[7]) {
   const T gm1_inv = T(1) / (gam - T(1));
   const T bn2 = bn * bn;
 

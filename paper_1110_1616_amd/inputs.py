@@ -457,3 +457,46 @@ def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1
         prim = [rho, v[0] * vscale, v[1] * vscale, v[2] * vscale, np.ones_like(rho)]
         out.append({"prim": prim, "b": [c * bscale for c in b]})
     return out
+
+
+def loss_box(ndim, n, size, seed):
+    """Seeded corner of a size^ndim box of cells on the periodic grid n (the
+    box may wrap).  Returns (lo, len) tuples over the active axes."""
+    rng = np.random.default_rng(seed)
+    lo = tuple(int(rng.integers(0, n[a])) for a in range(ndim))
+    return lo, (size,) * ndim
+
+
+def control_directions(shape, count, seed, scale=0.1):
+    """`count` seeded directions in (rho, vx, vy, vz): N(0, 1) entries
+    times `scale`, each a list of four arrays of `shape`."""
+    rng = np.random.default_rng(seed)
+    return [[scale * rng.normal(size=shape) for _ in range(4)] for _ in range(count)]
+
+
+def split_grid_fields(ic, boxes):
+    """Interior arrays of each sub-box (lo, hi) of a single-grid state `ic`
+    (cells, and the faces on and inside the sub-box)."""
+    ndim = ic["ndim"]
+    out = []
+    for lo, hi in boxes:
+        lo3 = tuple(lo) + (0,) * (3 - len(lo))
+        hi3 = tuple(hi) + (1,) * (3 - len(hi))
+        cs = (slice(lo3[2], hi3[2]), slice(lo3[1], hi3[1]), slice(lo3[0], hi3[0]))
+        prim = [np.ascontiguousarray(np.asarray(p).reshape(_cell_shape(ic))[cs]) for p in ic["prim"]]
+        b = []
+        for a in range(3):
+            sl = list(cs)
+            if a < ndim:
+                sl[2 - a] = slice(cs[2 - a].start, cs[2 - a].stop + 1)
+            arr = np.asarray(ic["b"][a])
+            if ndim == 2 and a == 2:
+                arr = arr.reshape(_cell_shape(ic))
+            b.append(np.ascontiguousarray(arr[tuple(sl)]))
+        out.append({"prim": prim, "b": b, "dx": ic["dx"], "ndim": ndim, "n": tuple(hi3[a] - lo3[a] for a in range(ndim))})
+    return out
+
+
+def _cell_shape(ic):
+    n = tuple(ic["n"]) + (1,) * (3 - len(ic["n"]))
+    return (n[2], n[1], n[0])

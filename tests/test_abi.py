@@ -95,3 +95,17 @@ def test_validate_rejects_broken_nesting():
     p2 = A.make_params(3, (16, 16, 16), nlevels=2, ghost=2)
     with pytest.raises(A.AmrError):
         A.amr_validate(p2, A.make_grids([(0, (0, 0, 0), (16, 16, 16)), (1, (8, 8, 8), (16, 16, 16))]))
+
+
+@pytest.mark.parametrize("which", range(7))
+def test_pointwise_adjoints_pass_the_dot_product_test(which):
+    """The hand-written reverse of each pointwise piece of the advance (host
+    instance of the same device code) equals the exact forward-mode
+    derivative: <a, J d> = <J^T a, d> on random physical states."""
+    import ctypes as C
+    L = A.lib()
+    L.amr_selfcheck_adjoint.restype = C.c_double
+    L.amr_selfcheck_adjoint.argtypes = [C.c_int32, C.c_int32, C.c_uint64]
+    err = L.amr_selfcheck_adjoint(which, 300, 1234 + which)
+    assert 0.0 <= err <= 1e-9, err
+    assert L.amr_selfcheck_adjoint(7, 10, 1) == -1.0
