@@ -1,6 +1,7 @@
 """Benchmark of the batched MHD patch advance on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+                [--no-adjoint] [--adjoint-only]
 
 Prints ONE JSON line.  `value` is useful cell-updates per second (one
 interior cell advanced by one (sub)step) of the whole step with inputs
@@ -188,6 +189,52 @@ def single_workload(args):
 WORKLOADS = {"amr3": amr_workload, "single128": single_workload}
 
 
+def adjoint_measure(reps=3):
+    """Cost of the discrete adjoint on the differentiation workload: 64^3
+    periodic FP64 grid, smooth Fourier-mode rho/v/A, 20 steps with step sizes
+    frozen from a CFL-0.4 forward run, checkpoints every 5 steps.  forward =
+    the differentiable advance (steps plus checkpoint copies); adjoint = its
+    backward (recompute of each segment plus the reverse sweep)."""
+    import numpy as np
+    import torch
+
+    from paper_1110_1616_amd import amr as A
+    from paper_1110_1616_amd import autodiff as AD
+    from paper_1110_1616_amd import inputs as I
+
+    n = (64, 64, 64)
+    ic = I.smooth_mhd(3, n, seed=4, v_rms=0.1, b_rms=0.3)
+    H = A.Hierarchy(3, n, [(0, (0, 0, 0), n)], ghost=2, dtype="f64", dx0=ic["dx"], gamma=GAMMA)
+    U, V = H.new_state(), H.new_state()
+    H.load_primitive(U, 0, ic["prim"], ic["b"])
+    U0 = [f.clone() for f in U.fields]
+    dts = []
+    for _ in range(20):
+        H.fill(0, A.AMR_FILL_SAME_LEVEL, U)
+        H.compute_dt(U)
+        dts.append(float(H.dt0.item()))
+        H.advance(U, V, cycle=0, band=2)
+        U, V = V, U
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    seed = [torch.randn(H.state_elems, dtype=torch.float64, device="cuda", generator=gen) for _ in range(8)]
+    fwd, bwd = [], []
+    for _ in range(reps + 1):
+        x = [f.clone().requires_grad_(True) for f in U0]
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record()
+        out = AD.advance(H, 0, dts, x, every=5)
+        e1.record()
+        torch.autograd.grad(out, x, grad_outputs=seed)
+        e2.record()
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+        bwd.append(e1.elapsed_time(e2))
+    f, b = float(np.median(fwd[1:])), float(np.median(bwd[1:]))
+    return {"workload": "64^3 periodic FP64, smooth Fourier-mode rho/v/A, 20 steps, checkpoints every 5",
+            "forward_ms": f, "adjoint_ms": b, "adjoint_over_forward": b / f}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +247,9 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint of the 64^3 differentiation workload and print that object")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -211,6 +261,9 @@ def main():
     from paper_1110_1616_amd import amr as A
 
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_measure(reps=max(1, args.steps))}), flush=True)
+        return
     W = WORKLOADS[args.workload](args)
     H, info = W["H"], W["info"]
 
@@ -292,6 +345,8 @@ def main():
     if per_grid is not None:
         out["per_grid_value"] = per_grid
         out["batched_over_per_grid"] = value / per_grid
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_measure()
     if not args.no_cpu_baseline:
         cs = W["cpu_sample"]()
         out["cpu_baseline"] = {"value": cs["updates"] / cs["seconds"], "unit": "cell-updates/s",

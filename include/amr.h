@@ -256,6 +256,21 @@ amr_status amr_advance_adjoint(amr_hierarchy* h, int32_t grid_or_level, int32_t 
 /* Workspace bytes amr_advance_adjoint() needs for that selection and nsteps. */
 amr_status amr_adjoint_workspace(const amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, int64_t* bytes);
 
+/* Frozen-branch advance, the finite-difference check of the adjoint: the
+ * map of amr_advance_adjoint() (per step a same-level band copy, then a
+ * band-2 step of every grid of `level` with level-0 step size dts[k]) applied
+ * to U_pert, with every branch of the scheme (minmod choices, wave-speed
+ * extremes and clamps, HLLD region and degeneracy tests) decided by the
+ * simultaneous unperturbed run from U_base.  Along such a fixed branch the
+ * map is smooth, so (J(U + eps d) - J(U - eps d)) / (2 eps) with both runs
+ * frozen on U agrees with the adjoint's <grad J, d> to O(eps^2) however many
+ * branch kinks lie within eps of U.  U_base is read; on exit U_pert's
+ * elements of the level's grids hold the perturbed result (other elements
+ * unchanged).  workspace: amr_frozen_workspace() bytes. */
+amr_status amr_advance_frozen(amr_hierarchy* h, int32_t level, int32_t nsteps, const double* dts,
+                              const amr_state* U_base, amr_state* U_pert, void* workspace, void* stream);
+amr_status amr_frozen_workspace(const amr_hierarchy* h, int64_t* bytes);
+
 /* Adjoint of amr_store_interior(): lambda's own elements of `grid` <- g, the
  * eight interior-layout float64 device arrays amr_store_interior() writes
  * (cells, then x-, y-, z-faces; in 2D g[7] is the cell Bz).  Band elements

@@ -78,6 +78,9 @@ def lib():
         L.amr_adjoint_workspace.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
         L.amr_store_interior_adjoint.argtypes = [_VP, C.c_int32, _PP, C.POINTER(amr_state), _VP]
         L.amr_load_primitive_adjoint.argtypes = [_VP, C.c_int32, _PP, C.POINTER(amr_state), _PP, _VP]
+        L.amr_frozen_workspace.argtypes = [_VP, C.POINTER(C.c_int64)]
+        L.amr_advance_frozen.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
+                                         C.POINTER(amr_state), _VP, _VP]
         L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
         L.amr_graph_capture.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP,
                                         C.c_int32, _VP]
@@ -226,6 +229,18 @@ def amr_load_primitive_adjoint(h, grid, prim, lam, grad):
     pp = (C.c_void_p * 4)(*[t.data_ptr() for t in prim[:4]])
     gg = (C.c_void_p * 4)(*[t.data_ptr() for t in grad])
     _check(lib().amr_load_primitive_adjoint(h, grid, pp, C.byref(lam), gg, _stream()), "amr_load_primitive_adjoint")
+
+
+def amr_frozen_workspace(h):
+    b = C.c_int64()
+    _check(lib().amr_frozen_workspace(h, C.byref(b)), "amr_frozen_workspace")
+    return b.value
+
+
+def amr_advance_frozen(h, level, dts, Ubase, Upert, ws):
+    d = (C.c_double * len(dts))(*[float(x) for x in dts])
+    _check(lib().amr_advance_frozen(h, level, len(dts), d, C.byref(Ubase), C.byref(Upert), _ptr(ws), _stream()),
+           "amr_advance_frozen")
 
 
 def amr_get_error_flags(h):

@@ -13,6 +13,7 @@
 #include "advance_common.hpp"
 #include "amr_internal.hpp"
 #include "emf.hpp"
+#include "frozen.hpp"
 #include "mhd_device.hpp"
 
 namespace amr {
@@ -299,5 +300,14 @@ template void launch_update<float>(int, const GridDesc*, const UpdItem*, int, De
                                    uint32_t, DevFlux<float>, const double*, Phys, hipStream_t);
 template void launch_update<double>(int, const GridDesc*, const UpdItem*, int, DevState<double>, DevState<double>,
                                     uint32_t, DevFlux<double>, const double*, Phys, hipStream_t);
+// frozen-branch instances (finite-difference verification of the adjoint)
+template void launch_flux<FrozenD>(int, const GridDesc*, const FluxItem*, int, DevState<FrozenD>, DevState<FrozenD>,
+                                   uint32_t, DevFlux<FrozenD>, const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_flux<FrozenF>(int, const GridDesc*, const FluxItem*, int, DevState<FrozenF>, DevState<FrozenF>,
+                                   uint32_t, DevFlux<FrozenF>, const double*, Phys, ErrBlock*, hipStream_t);
+template void launch_update<FrozenD>(int, const GridDesc*, const UpdItem*, int, DevState<FrozenD>,
+                                     DevState<FrozenD>, uint32_t, DevFlux<FrozenD>, const double*, Phys, hipStream_t);
+template void launch_update<FrozenF>(int, const GridDesc*, const UpdItem*, int, DevState<FrozenF>,
+                                     DevState<FrozenF>, uint32_t, DevFlux<FrozenF>, const double*, Phys, hipStream_t);
 
 }  // namespace amr

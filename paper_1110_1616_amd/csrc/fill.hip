@@ -7,6 +7,7 @@
 // reconstructed from.  Every band element has exactly one writer.
 #include "amr_internal.hpp"
 #include "fill_internal.hpp"
+#include "frozen.hpp"
 #include "mhd_device.hpp"
 
 namespace amr {
@@ -359,5 +360,7 @@ void launch_store(int ndim, const GridDesc& G, DevState<T> U, double* const* out
 AMR_INST(float)
 AMR_INST(double)
 #undef AMR_INST
+template void launch_copy<FrozenD>(int, const CopyEntry*, int, int4, DevState<FrozenD>, hipStream_t);
+template void launch_copy<FrozenF>(int, const CopyEntry*, int, int4, DevState<FrozenF>, hipStream_t);
 
 }  // namespace amr

@@ -20,6 +20,7 @@
 #include "adjoint_internal.hpp"
 #include "amr_internal.hpp"
 #include "fill_internal.hpp"
+#include "frozen_internal.hpp"
 #include "sync_internal.hpp"
 
 using namespace amr;
@@ -1511,9 +1512,79 @@ void adjoint_run(amr_hierarchy* h, int level, int nsteps, const double* dts, con
                             (t.e1 - t.e0) * (int64_t)sizeof(T), hipMemcpyDeviceToDevice, s));
 }
 
+// Frozen-branch advance: pairs (base, perturbed) in workspace, the same
+// fill + band-2 step sequence as the adjoint's forward map.
+int64_t frozen_workspace(const amr_hierarchy* h) {
+  const int64_t es2 = 2 * (int64_t)h->esize;
+  return align256(21 * h->total_elems * es2) + 2 * align256(8 * h->total_elems * es2) + 256;
+}
+
+template <class S>
+void frozen_run(amr_hierarchy* h, int level, int nsteps, const double* dts, const amr_state* Ub, amr_state* Up,
+                void* ws, hipStream_t s) {
+  using P = Frozen<S>;
+  char* base = (char*)ws;
+  const int64_t arr = h->total_elems * (int64_t)sizeof(P);
+  const int64_t off_s0 = align256(21 * arr);
+  const int64_t off_s1 = off_s0 + align256(8 * arr);
+  double* d_dt = (double*)(off_s1 + align256(8 * arr) + base);
+  amr_state st[2];
+  for (int q = 0; q < 8; ++q) {
+    st[0].f[q] = base + off_s0 + q * arr;
+    st[1].f[q] = base + off_s1 + q * arr;
+  }
+  launch_pack<S>(dstate<S>(Ub), dstate<S>(Up), dstate<P>(&st[0]), h->total_elems, s);
+  launch_pack<S>(dstate<S>(Ub), dstate<S>(Up), dstate<P>(&st[1]), h->total_elems, s);
+  HIPCHK(hipGetLastError());
+  const bool timing = h->timing;
+  h->timing = false;
+  int cur = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    launch_put_values(d_dt, dts + k, 1, s);
+    launch_copy<P>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<P>(&st[cur]), s);
+    HIPCHK(hipGetLastError());
+    run_list<P>(h, h->band2_lists[level], &st[cur], &st[1 - cur], 0u, d_dt, ws, s);
+    cur = 1 - cur;
+  }
+  h->timing = timing;
+  int64_t e0 = INT64_MAX, e1 = 0;
+  for (int gi : h->level_grids[level]) {
+    const GridDesc& G = h->desc[gi];
+    e0 = std::min<int64_t>(e0, G.off);
+    e1 = std::max<int64_t>(e1, G.off + (int64_t)G.P[0] * G.P[1] * G.P[2]);
+  }
+  launch_unpack<S>(dstate<P>(&st[cur]), dstate<S>(Up), e0, e1, s);
+  HIPCHK(hipGetLastError());
+}
+
 }  // namespace
 
 extern "C" {
+
+amr_status amr_frozen_workspace(const amr_hierarchy* h, int64_t* bytes) {
+  if (!h || !bytes) return AMR_EINVAL;
+  *bytes = frozen_workspace(h);
+  return AMR_OK;
+}
+
+amr_status amr_advance_frozen(amr_hierarchy* h, int32_t level, int32_t nsteps, const double* dts,
+                              const amr_state* U_base, amr_state* U_pert, void* workspace, void* stream) {
+  try {
+    if (!h || !dts || !U_base || !U_pert || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (level < 0 || level >= h->nlev) throw Error(AMR_EINVAL, "level out of range");
+    if (nsteps < 1) throw Error(AMR_EINVAL, "nsteps must be >= 1");
+    for (int k = 0; k < nsteps; ++k)
+      if (!(dts[k] > 0.0)) throw Error(AMR_EINVAL, "step sizes must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (h->esize == 8)
+      frozen_run<double>(h, level, nsteps, dts, U_base, U_pert, workspace, s);
+    else
+      frozen_run<float>(h, level, nsteps, dts, U_base, U_pert, workspace, s);
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
 
 amr_status amr_adjoint_workspace(const amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, int64_t* bytes) {
   try {

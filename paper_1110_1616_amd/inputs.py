@@ -500,3 +500,35 @@ def split_grid_fields(ic, boxes):
 def _cell_shape(ic):
     n = tuple(ic["n"]) + (1,) * (3 - len(ic["n"]))
     return (n[2], n[1], n[0])
+
+
+def smooth_directions(n, count, seed, kmax=2, nmodes=4, scale=0.1):
+    """`count` seeded smooth directions in (rho, vx, vy, vz) on the periodic
+    grid n (cell centres): per field a sum of `nmodes` Fourier modes with
+    integer wavevectors |k_a| <= kmax, N(0, 1) amplitudes and uniform phases,
+    rescaled to rms `scale`."""
+    rng = np.random.default_rng(seed)
+    ndim = len(n)
+    ax = [(np.arange(n[a]) + 0.5) / n[a] for a in range(ndim)]
+    if ndim == 3:
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    else:
+        Y, X = np.meshgrid(ax[1], ax[0], indexing="ij")
+        Y, X = Y[None], X[None]
+        Z = np.zeros_like(X)
+    out = []
+    for _ in range(count):
+        d = []
+        for _q in range(4):
+            f = np.zeros_like(X)
+            for _m in range(nmodes):
+                k = rng.integers(-kmax, kmax + 1, size=3)
+                if ndim == 2:
+                    k[2] = 0
+                if not np.any(k):
+                    k[0] = 1
+                f += rng.normal() * np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + rng.uniform(0, 2 * np.pi))
+            f *= scale / np.sqrt(np.mean(f * f))
+            d.append(f)
+        out.append(d)
+    return out
