@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
+                         "calibrates HBM byte counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the adjoint of the 64^3 differentiation workload and print that object")
     args = ap.parse_args()
@@ -261,6 +264,14 @@ def main():
     from paper_1110_1616_amd import amr as A
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_measure(reps=max(1, args.steps))}), flush=True)
         return

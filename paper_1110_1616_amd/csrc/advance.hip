@@ -20,27 +20,29 @@ namespace amr {
 
 namespace {
 
-constexpr int kW = 18;  // LDS plane edge: 16 thread columns + 1 ring cell each side
+// A flux tile is tw x th threads (tw in [kMinTile, kMaxTile], th = 256 / tw)
+// over cells (x0-1+tx, y0-1+ty); the LDS plane adds one ring cell on each
+// side: (tw+2) x (th+2) entries, at most kMaxPlane.
+constexpr int kMaxPlane = 396;  // max over tw in [4, 64] of (tw + 2)(256 / tw + 2)
 
-// Ring entry r in [0, 68) of the 18x18 LDS plane -> (ex, ey).
-__device__ __forceinline__ void ring_entry(int r, int& ex, int& ey) {
-  if (r < 18) { ex = r; ey = 0; }
-  else if (r < 36) { ex = r - 18; ey = 17; }
-  else if (r < 52) { ex = 0; ey = r - 35; }
-  else { ex = 17; ey = r - 51; }
+// Ring entry r in [0, 2(tw+2) + 2 th) of the plane -> (ex, ey).
+__device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& ey) {
+  const int w2 = tw + 2;
+  if (r < w2) { ex = r; ey = 0; }
+  else if (r < 2 * w2) { ex = r - w2; ey = th + 1; }
+  else if (r < 2 * w2 + th) { ex = 0; ey = r - 2 * w2 + 1; }
+  else { ex = tw + 1; ey = r - 2 * w2 - th + 1; }
 }
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                               DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err) {
-  __shared__ T sW[8][kW * kW];
+  __shared__ T sW[8][kMaxPlane];
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
 
   const int tid = threadIdx.x;
-  const int tx = tid & 15;
-  const int ty = tid >> 4;
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
 
@@ -55,8 +57,11 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     const int chx = G.n[0] + gv - 1, chy = G.n[1] + gv - 1;
     const int wlo = -gv, whix = G.n[0] + gv, whiy = G.n[1] + gv;  // valid input cells [wlo, whi)
     const int x0 = item.x0, y0 = item.y0;
+    const int tw = item.tw, th = 256 / tw, kW = tw + 2;
+    const int tx = tid % tw, ty = tid / tw;
+    const bool live = ty < th;
     const int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
-    const bool act = cx >= cl && cx < chx && cy >= cl && cy < chy;
+    const bool act = live && cx >= cl && cx < chx && cy >= cl && cy < chy;
     const bool own = act && tx >= 1 && ty >= 1;
 
     // time step of this grid's level and 1/dx
@@ -69,13 +74,14 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     idx[1] = T(rl / ph.dx0[1]);
     idx[2] = T(NDIM == 3 ? rl / ph.dx0[2] : 0.0);
 
-    // own LDS entry and (for tid < 68) one ring entry
+    // own LDS entry and (for the first nring threads) one ring entry
     const int eo = (ty + 1) * kW + tx + 1;
+    const int nring = 2 * (tw + 2) + 2 * th;
     int rex = 0, rey = 0;
-    if (tid < 68) ring_entry(tid, rex, rey);
+    if (tid < nring) ring_entry(tid, tw, th, rex, rey);
     const int rcx = x0 - 2 + rex, rcy = y0 - 2 + rey;
-    const bool rok = tid < 68 && rcx >= wlo && rcx < whix && rcy >= wlo && rcy < whiy;
-    const bool ook = cx >= wlo && cx < whix && cy >= wlo && cy < whiy;
+    const bool rok = tid < nring && rcx >= wlo && rcx < whix && rcy >= wlo && rcy < whiy;
+    const bool ook = live && cx >= wlo && cx < whix && cy >= wlo && cy < whiy;
 
     const int kstart = NDIM == 3 ? max(item.z0 - 1, cl) : 0;
     const int kend = NDIM == 3 ? item.z1 : 1;
@@ -93,8 +99,8 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, kstart), ix.sy, ix.sz, gm1, wring);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      sW[q][eo] = wcur[q];
-      if (tid < 68) sW[q][rey * kW + rex] = wring[q];
+      if (live) sW[q][eo] = wcur[q];
+      if (tid < nring) sW[q][rey * kW + rex] = wring[q];
     }
     __syncthreads();
 
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
         if (cy > cl) {
           T l[7];
 #pragma unroll
-          for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - 16];
+          for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - tw];
           hlld7(l, pr.m[1], U.f[6][e], gam, f);
 #pragma unroll
           for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
@@ -169,8 +175,8 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
       if (NDIM == 3) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          sW[q][eo] = wnext[q];
-          if (tid < 68) sW[q][rey * kW + rex] = wring[q];
+          if (live) sW[q][eo] = wnext[q];
+          if (tid < nring) sW[q][rey * kW + rex] = wring[q];
           wprev[q] = wcur[q];
           wcur[q] = wnext[q];
         }
@@ -184,8 +190,7 @@ template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
                                                 int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                                 DevFlux<T> F, const double* __restrict__ dt0p, Phys ph) {
-  const int tx = threadIdx.x & 15;
-  const int ty = threadIdx.x >> 4;
+  const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const UpdItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -195,6 +200,9 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
     const Idx<NDIM> ix(G);
     const int gv = item.gv;
     const int uhx = G.n[0] + gv - 2, uhy = G.n[1] + gv - 2, uhz = NDIM == 3 ? G.n[2] + gv - 2 : 0;
+    const int tw = item.tw, th = 256 / tw;
+    const int tx = tid % tw, ty = tid / tw;
+    if (ty >= th) continue;
     const int cx = item.x0 + tx, cy = item.y0 + ty;
     if (cx > uhx || cy > uhy) continue;
 

@@ -64,12 +64,15 @@ struct Pred {
 
 // Slopes, face states, Hancock increment and predicted states of one cell.
 // wx/wy/wz hold the neighbours (minus, plus) along each axis; fb[d][0/1] are
-// the cell's low/high face fields along d.
-template <class T, int NDIM>
-__device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8], const T (&wym)[8],
-                                        const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
-                                        const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
-                                        Pred<T, NDIM>& out) {
+// the cell's low/high face fields along d.  Each predicted state is handed to
+// emit(d, side, q) as soon as it is formed (side 0 low, 1 high), so callers
+// that store it right away never hold all 2*NDIM states in registers.
+// Returns false if a predicted density or pressure is not positive.
+template <class T, int NDIM, class Emit>
+__device__ __forceinline__ bool predict_emit(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8],
+                                             const T (&wym)[8], const T (&wyp)[8], const T (&wzm)[8],
+                                             const T (&wzp)[8], const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
+                                             Emit&& emit) {
   const T gm1 = gam - T(1);
   const T gm1_inv = T(1) / gm1;
   T sl[3][8];
@@ -121,13 +124,26 @@ __device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], cons
       for (int q = 0; q < 8; ++q) us[q] += du[q];
       to_primitive(us, wb, gm1);
       ok = ok && (wb[0] > T(0)) && (wb[4] > T(0));
-      T(&dst)[7] = side ? out.p[d] : out.m[d];
-      if (d == 0) rotate7<0>(wb, dst);
-      else if (d == 1) rotate7<1>(wb, dst);
-      else rotate7<2>(wb, dst);
+      T q7[7];
+      if (d == 0) rotate7<0>(wb, q7);
+      else if (d == 1) rotate7<1>(wb, q7);
+      else rotate7<2>(wb, q7);
+      emit(d, side, q7);
     }
   }
   return ok;
+}
+
+template <class T, int NDIM>
+__device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8], const T (&wym)[8],
+                                        const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
+                                        const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
+                                        Pred<T, NDIM>& out) {
+  return predict_emit<T, NDIM>(w, wxm, wxp, wym, wyp, wzm, wzp, fb, hdt, idx, gam,
+                               [&](int d, int side, const T (&q)[7]) {
+#pragma unroll
+                                 for (int c = 0; c < 7; ++c) (side ? out.p[d] : out.m[d])[c] = q[c];
+                               });
 }
 
 template <class T>

@@ -19,26 +19,33 @@ struct GridDesc {
   int64_t off;
 };
 
-// Flux-kernel work item: one 15x15-cell column tile of one grid, owned
-// planes [z0, z1), advanced from valid band gv.  (x0, y0) is the first owned
-// cell of the tile.
+// Flux-kernel work item: one column tile of one grid, owned planes
+// [z0, z1), advanced from valid band gv.  The block's 256 threads form
+// tw x (256 / tw) cells (x0-1+tx, y0-1+ty); the first column and row overlap
+// the neighbouring tiles, so (x0, y0) is the first owned cell and the tile
+// owns (tw-1) x (256/tw - 1) cells of each plane.
 struct FluxItem {
   int32_t grid;
   int32_t gv;
   int32_t x0, y0;
   int32_t z0, z1;
-  int32_t pad0, pad1;
+  int32_t tw;
+  int32_t pad;
 };
 
-// Update-kernel work item: a 16x16-column tile of the update index box
-// starting at (x0, y0), planes [z0, z1).
+// Update-kernel work item: a tw x (256 / tw) column tile of the update index
+// box starting at (x0, y0), planes [z0, z1).
 struct UpdItem {
   int32_t grid;
   int32_t gv;
   int32_t x0, y0;
   int32_t z0, z1;
-  int32_t pad0, pad1;
+  int32_t tw;
+  int32_t pad;
 };
+
+constexpr int kMinTile = 4;   // tile widths the kernels accept
+constexpr int kMaxTile = 64;
 
 // Physics constants passed by value.
 struct Phys {
@@ -67,8 +74,6 @@ struct ErrBlock {
   int64_t first_bad;
 };
 
-constexpr int kFluxTile = 15;  // owned cells per tile edge of the flux kernel
-constexpr int kUpdTile = 16;   // cells per tile edge of the update kernel
 
 // Host-side launchers (defined in the .hip translation units).
 // Level l of a grid reads its state from S1 if bit l of `parity` is set,

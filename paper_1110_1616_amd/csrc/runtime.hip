@@ -122,6 +122,7 @@ struct amr_hierarchy {
   };
   std::vector<AdjTables> adj;
   int zchunk = 16;
+  int tile_policy = 1;  // 0: 16 x 16 tiles; 1: per-grid width with the fewest tiles
 
   // captured coarse steps: graph[p] starts from level-0 parity bit p
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -270,6 +271,31 @@ void validate(const amr_params* p, const amr_grid* grids, int ngrids) {
 }
 
 // ------------------------------------------------------------ work lists
+// Tile width for a W x H region covered by 256-thread tiles of tw x (256/tw)
+// threads that overlap their neighbours by `ov` cells: policy 0 takes 16 x 16;
+// policy 1 the width that launches the fewest tiles (wider on ties, for
+// longer coalesced rows).
+int pick_tile(int W, int H, int ov, int policy) {
+  if (policy == 0) return 16;
+  int best = 16;
+  int64_t bc = INT64_MAX;
+  for (int tw = kMaxTile; tw >= kMinTile; --tw) {
+    const int th = 256 / tw;
+    if (th - ov < 1 || tw - ov < 1) continue;
+    const int64_t c = (int64_t)((W + tw - ov - 1) / (tw - ov)) * ((H + th - ov - 1) / (th - ov));
+    if (c < bc) {
+      bc = c;
+      best = tw;
+    }
+  }
+  return best;
+}
+
+void check_tile(int tw) {
+  if (tw < kMinTile || tw > kMaxTile) throw Error(AMR_EINVAL, "internal: tile width out of range");
+  if ((tw + 2) * (256 / tw + 2) > 396) throw Error(AMR_EINVAL, "internal: tile plane exceeds the LDS plane");
+}
+
 void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl, std::vector<UpdItem>& ul) {
   const GridDesc& G = h->desc[gi];
   const int cl = -gv + 1;
@@ -280,10 +306,13 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   }
   const int zc = h->zchunk;
   const int zlo = h->ndim == 3 ? cl : 0;
+  const int ftw = pick_tile(ch[0] - cl, ch[1] - cl, 1, h->tile_policy), fth = 256 / ftw;
+  check_tile(ftw);
   for (int z0 = zlo; z0 < ch[2]; z0 += (h->ndim == 3 ? zc : 1))
-    for (int y0 = cl; y0 < ch[1]; y0 += kFluxTile)
-      for (int x0 = cl; x0 < ch[0]; x0 += kFluxTile) {
+    for (int y0 = cl; y0 < ch[1]; y0 += fth - 1)
+      for (int x0 = cl; x0 < ch[0]; x0 += ftw - 1) {
         FluxItem it{};
+        it.tw = ftw;
         it.grid = gi;
         it.gv = gv;
         it.x0 = x0;
@@ -295,10 +324,13 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   const int ul0 = -gv + 2;
   const int uzlo = h->ndim == 3 ? ul0 : 0;
   const int uzhi = h->ndim == 3 ? uh[2] + 1 : 1;
+  const int utw = pick_tile(uh[0] - ul0 + 1, uh[1] - ul0 + 1, 0, h->tile_policy), uth = 256 / utw;
+  check_tile(utw);
   for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? zc : 1))
-    for (int y0 = ul0; y0 <= uh[1]; y0 += kUpdTile)
-      for (int x0 = ul0; x0 <= uh[0]; x0 += kUpdTile) {
+    for (int y0 = ul0; y0 <= uh[1]; y0 += uth)
+      for (int x0 = ul0; x0 <= uh[0]; x0 += utw) {
         UpdItem it{};
+        it.tw = utw;
         it.grid = gi;
         it.gv = gv;
         it.x0 = x0;
