@@ -98,7 +98,10 @@ def single_grid_workload(args):
         return {"seconds": t, "updates": float(N ** 3 * steps), "threads": O.max_threads(),
                 "sample": f"oracle, same {N}^3 input, first {steps} steps (band 4 refilled every 2 steps)"}
 
-    return H, step, (lambda k: flops_per_step_pair * k / 2.0), info, cpu_sample
+    def tune():
+        return H.autotune(state["U"], state["V"], 0, reps=3)
+
+    return H, step, (lambda k: flops_per_step_pair * k / 2.0), info, cpu_sample, tune
 
 
 def amr_workload(args):
@@ -148,6 +151,10 @@ def amr_workload(args):
         with torch.cuda.stream(stream):
             st["par"] = H.graph_launch(st["par"])
 
+    def tune():
+        with torch.cuda.stream(stream):
+            return H.autotune(Ua, Ub, st["par"], reps=3)
+
     info = {
         "workload": f"3-level AMR hierarchy, R=2, 3D ideal MHD {args.dtype}: base {args.n0}^3 tiled by {len(grids)} grids "
                     f"of even extents 8..32 (levels {cells} cells), each level covering 12.5% of its parent, "
@@ -177,13 +184,14 @@ def amr_workload(args):
                           f"{len(g2)} grids), {steps} coarse steps"}
 
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
-            "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample}
+            "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
+            "tune": tune}
 
 
 def single_workload(args):
-    H, step, flops, info, cpu = single_grid_workload(args)
+    H, step, flops, info, cpu, tune = single_grid_workload(args)
     return {"H": H, "stream": None, "step": step, "prepare": None, "eager": step, "per_grid": None,
-            "flux_flops": flops, "info": info, "cpu_sample": cpu}
+            "flux_flops": flops, "info": info, "cpu_sample": cpu, "tune": tune}
 
 
 WORKLOADS = {"amr3": amr_workload, "single128": single_workload}
@@ -248,6 +256,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")
@@ -295,6 +304,16 @@ def main():
     for _ in range(args.warmup):
         W["eager"]()
     torch.cuda.synchronize()
+    tuned = None
+    if W.get("tune") and not args.no_autotune:
+        chosen, table = W["tune"]()
+        torch.cuda.synchronize()
+        tuned = {"chosen": {"tile_policy": table[chosen][0], "zchunk": table[chosen][1],
+                            "persistent": table[chosen][2]},
+                 "candidates_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
+        for _ in range(2):
+            W["eager"]()
+        torch.cuda.synchronize()
     if W["prepare"]:
         W["prepare"]()
         torch.cuda.synchronize()
@@ -356,6 +375,8 @@ def main():
     if per_grid is not None:
         out["per_grid_value"] = per_grid
         out["batched_over_per_grid"] = value / per_grid
+    if tuned is not None:
+        out["autotune"] = tuned
     if not args.no_adjoint:
         out["adjoint"] = adjoint_measure()
     if not args.no_cpu_baseline:

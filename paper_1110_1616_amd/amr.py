@@ -39,6 +39,11 @@ class amr_state(C.Structure):
     _fields_ = [("f", C.c_void_p * 8)]
 
 
+class amr_tune_entry(C.Structure):
+    _fields_ = [("tile_policy", C.c_int32), ("zchunk", C.c_int32), ("persistent", C.c_int32), ("pad", C.c_int32),
+                ("ms", C.c_double)]
+
+
 class AmrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -81,6 +86,10 @@ def lib():
         L.amr_frozen_workspace.argtypes = [_VP, C.POINTER(C.c_int64)]
         L.amr_advance_frozen.argtypes = [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(amr_state),
                                          C.POINTER(amr_state), _VP, _VP]
+        L.amr_set_launch_config.argtypes = [_VP, C.c_int32, C.c_int32, C.c_int32]
+        L.amr_get_launch_config.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.amr_autotune.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP, C.c_int32,
+                                   C.POINTER(amr_tune_entry), C.POINTER(C.c_int32), _VP]
         L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
         L.amr_graph_capture.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP,
                                         C.c_int32, _VP]
@@ -243,6 +252,25 @@ def amr_advance_frozen(h, level, dts, Ubase, Upert, ws):
            "amr_advance_frozen")
 
 
+def amr_set_launch_config(h, tile_policy, zchunk, persistent):
+    _check(lib().amr_set_launch_config(h, tile_policy, zchunk, int(bool(persistent))), "amr_set_launch_config")
+
+
+def amr_get_launch_config(h):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().amr_get_launch_config(h, C.byref(a), C.byref(b), C.byref(c)), "amr_get_launch_config")
+    return a.value, b.value, c.value
+
+
+def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):
+    """Returns (chosen index, [(tile_policy, zchunk, persistent, ms), ...])."""
+    res = (amr_tune_entry * 16)()
+    ch = C.c_int32()
+    _check(lib().amr_autotune(h, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws), reps, res, C.byref(ch),
+                              _stream()), "amr_autotune")
+    return ch.value, [(r.tile_policy, r.zchunk, r.persistent, r.ms) for r in res]
+
+
 def amr_get_error_flags(h):
     fl = C.c_uint32()
     bad = C.c_int64()
@@ -369,6 +397,12 @@ class Hierarchy:
 
     def graph_launch(self, parity):
         return amr_graph_launch(self.h, parity)
+
+    def autotune(self, Ua, Ub, parity, reps=3):
+        return amr_autotune(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, reps)
+
+    def set_launch_config(self, tile_policy, zchunk, persistent):
+        amr_set_launch_config(self.h, tile_policy, zchunk, persistent)
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua

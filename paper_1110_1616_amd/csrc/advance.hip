@@ -10,6 +10,8 @@
 // Work lists hold tiles of any number of grids of any level; the kernels
 // read each tile's grid descriptor, so one launch covers every grid that
 // steps in a launch cycle.
+#include <algorithm>
+
 #include "advance_common.hpp"
 #include "amr_internal.hpp"
 #include "emf.hpp"
@@ -34,11 +36,48 @@ __device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& 
   else { ex = tw + 1; ey = r - 2 * w2 - th + 1; }
 }
 
-template <class T, int NDIM>
+// Next work item of this block.  Grid-stride launches take blockIdx.x,
+// blockIdx.x + gridDim.x, ...; persistent launches (a fixed number of blocks)
+// pop the shared queue, one atomic per item, in list order (finest level
+// first), so blocks that draw cheap items come back for more.  Returns -1
+// when the list is exhausted.
+template <bool PERSIST>
+__device__ __forceinline__ int next_item(int& cursor, int nitems, WorkQueue* q, int* s_it) {
+  if (!PERSIST) {
+    const int it = cursor;
+    cursor += gridDim.x;
+    return it < nitems ? it : -1;
+  }
+  if (threadIdx.x == 0) *s_it = (int)atomicAdd(&q->head, 1u);
+  __syncthreads();
+  const int it = *s_it;
+  __syncthreads();
+  return it < nitems ? it : -1;
+}
+
+// Persistent launches leave the queue ready for the next one: the last block
+// to finish resets both counters (every other block has made its final pop
+// before it counts itself done).
+template <bool PERSIST>
+__device__ __forceinline__ void retire(WorkQueue* q) {
+  if (!PERSIST) return;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned d = atomicAdd(&q->done, 1u);
+    if (d == gridDim.x - 1) {
+      atomicExch(&q->head, 0u);
+      atomicExch(&q->done, 0u);
+    }
+  }
+}
+
+template <class T, int NDIM, bool PERSIST>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
-                                              DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err) {
+                                              DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err,
+                                              WorkQueue* q) {
   __shared__ T sW[8][kMaxPlane];
+  __shared__ int s_it;
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
 
@@ -46,7 +85,10 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
 
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  int cursor = blockIdx.x;
+  for (;;) {
+    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it);
+    if (it < 0) break;
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
     // each level's current data lives in S0 or S1 (bit `level` of parity)
@@ -184,14 +226,19 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
       }
     }
   }
+  retire<PERSIST>(q);
 }
 
-template <class T, int NDIM>
+template <class T, int NDIM, bool PERSIST>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
                                                 int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
-                                                DevFlux<T> F, const double* __restrict__ dt0p, Phys ph) {
+                                                DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, WorkQueue* q) {
+  __shared__ int s_it;
   const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  int cursor = blockIdx.x;
+  for (;;) {
+    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it);
+    if (it < 0) break;
     const UpdItem item = items[it];
     const GridDesc G = grids[item.grid];
     const bool odd = (parity >> G.level) & 1u;
@@ -272,50 +319,78 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
       }
     }
   }
+  retire<PERSIST>(q);
 }
 
 }  // namespace
 
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
-                 uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, hipStream_t s) {
+                 uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
+                 hipStream_t s) {
   if (nitems <= 0) return;
-  if (ndim == 3)
-    hipLaunchKernelGGL((k_flux<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph,
-                       err);
-  else
-    hipLaunchKernelGGL((k_flux<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph,
-                       err);
+  const bool per = pblocks > 0 && q != nullptr;
+  const dim3 grid(per ? std::min(pblocks, nitems) : nitems), block(256);
+  if (ndim == 3) {
+    if (per)
+      hipLaunchKernelGGL((k_flux<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+    else
+      hipLaunchKernelGGL((k_flux<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+  } else {
+    if (per)
+      hipLaunchKernelGGL((k_flux<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+    else
+      hipLaunchKernelGGL((k_flux<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+  }
 }
 
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
-                   uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, hipStream_t s) {
+                   uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
+                   hipStream_t s) {
   if (nitems <= 0) return;
-  if (ndim == 3)
-    hipLaunchKernelGGL((k_update<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0,
-                       ph);
-  else
-    hipLaunchKernelGGL((k_update<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, F, dt0,
-                       ph);
+  const bool per = pblocks > 0 && q != nullptr;
+  const dim3 grid(per ? std::min(pblocks, nitems) : nitems), block(256);
+  if (ndim == 3) {
+    if (per)
+      hipLaunchKernelGGL((k_update<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+    else
+      hipLaunchKernelGGL((k_update<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+  } else {
+    if (per)
+      hipLaunchKernelGGL((k_update<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+    else
+      hipLaunchKernelGGL((k_update<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+  }
 }
 
-template void launch_flux<float>(int, const GridDesc*, const FluxItem*, int, DevState<float>, DevState<float>,
-                                 uint32_t, DevFlux<float>, const double*, Phys, ErrBlock*, hipStream_t);
-template void launch_flux<double>(int, const GridDesc*, const FluxItem*, int, DevState<double>, DevState<double>,
-                                  uint32_t, DevFlux<double>, const double*, Phys, ErrBlock*, hipStream_t);
-template void launch_update<float>(int, const GridDesc*, const UpdItem*, int, DevState<float>, DevState<float>,
-                                   uint32_t, DevFlux<float>, const double*, Phys, hipStream_t);
-template void launch_update<double>(int, const GridDesc*, const UpdItem*, int, DevState<double>, DevState<double>,
-                                    uint32_t, DevFlux<double>, const double*, Phys, hipStream_t);
+// Resident 256-thread blocks per CU of each kernel (for persistent launches).
+template <class T>
+void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu) {
+  int a = 0, b = 0;
+  if (ndim == 3) {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 3, true>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 3, true>, 256, 0);
+  } else {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 2, true>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 2, true>, 256, 0);
+  }
+  *flux_blocks_per_cu = a > 0 ? a : 1;
+  *update_blocks_per_cu = b > 0 ? b : 1;
+}
+
+#define AMR_ADV_INST(T)                                                                                             \
+  template void launch_flux<T>(int, const GridDesc*, const FluxItem*, int, DevState<T>, DevState<T>, uint32_t,     \
+                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, hipStream_t);          \
+  template void launch_update<T>(int, const GridDesc*, const UpdItem*, int, DevState<T>, DevState<T>, uint32_t,   \
+                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, hipStream_t);
+AMR_ADV_INST(float)
+AMR_ADV_INST(double)
 // frozen-branch instances (finite-difference verification of the adjoint)
-template void launch_flux<FrozenD>(int, const GridDesc*, const FluxItem*, int, DevState<FrozenD>, DevState<FrozenD>,
-                                   uint32_t, DevFlux<FrozenD>, const double*, Phys, ErrBlock*, hipStream_t);
-template void launch_flux<FrozenF>(int, const GridDesc*, const FluxItem*, int, DevState<FrozenF>, DevState<FrozenF>,
-                                   uint32_t, DevFlux<FrozenF>, const double*, Phys, ErrBlock*, hipStream_t);
-template void launch_update<FrozenD>(int, const GridDesc*, const UpdItem*, int, DevState<FrozenD>,
-                                     DevState<FrozenD>, uint32_t, DevFlux<FrozenD>, const double*, Phys, hipStream_t);
-template void launch_update<FrozenF>(int, const GridDesc*, const UpdItem*, int, DevState<FrozenF>,
-                                     DevState<FrozenF>, uint32_t, DevFlux<FrozenF>, const double*, Phys, hipStream_t);
+AMR_ADV_INST(FrozenD)
+AMR_ADV_INST(FrozenF)
+#undef AMR_ADV_INST
+template void kernel_occupancy<float>(int, int*, int*);
+template void kernel_occupancy<double>(int, int*, int*);
 
 }  // namespace amr

@@ -123,6 +123,9 @@ struct amr_hierarchy {
   std::vector<AdjTables> adj;
   int zchunk = 16;
   int tile_policy = 1;  // 0: 16 x 16 tiles; 1: per-grid width with the fewest tiles
+  bool persistent = false;     // persistent launches popping d_queue, or one block per item
+  WorkQueue* d_queue = nullptr;
+  int flux_pblocks = 0, upd_pblocks = 0;  // persistent grid sizes (resident blocks on the device)
 
   // captured coarse steps: graph[p] starts from level-0 parity bit p
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -152,6 +155,7 @@ struct amr_hierarchy {
     (void)hipFree(d_uitems);
     (void)hipFree(d_cfl);
     (void)hipFree(d_err);
+    (void)hipFree(d_queue);
     for (auto p : d_copy) (void)hipFree(p);
     for (auto p : d_pcell) (void)hipFree(p);
     for (auto p : d_pface) (void)hipFree(p);
@@ -910,10 +914,12 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     e2 = h->take_event();
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
-  launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err, s);
+  launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
+                 h->d_queue, h->persistent ? h->flux_pblocks : 0, s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
-  launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, s);
+  launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, h->d_queue,
+                   h->persistent ? h->upd_pblocks : 0, s);
   HIPCHK(hipGetLastError());
   if (timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
@@ -1107,6 +1113,20 @@ amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids
     h = build_hierarchy(p, grids, ngrids);
     HIPCHK(hipMalloc((void**)&h->d_err, 256));
     HIPCHK(hipMemset(h->d_err, 0, 256));
+    HIPCHK(hipMalloc((void**)&h->d_queue, sizeof(WorkQueue)));
+    HIPCHK(hipMemset(h->d_queue, 0, sizeof(WorkQueue)));
+    {
+      int dev = 0, fb = 1, ub = 1;
+      HIPCHK(hipGetDevice(&dev));
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDeviceProperties(&prop, dev));
+      if (h->esize == 8)
+        kernel_occupancy<double>(h->ndim, &fb, &ub);
+      else
+        kernel_occupancy<float>(h->ndim, &fb, &ub);
+      h->flux_pblocks = prop.multiProcessorCount * fb;
+      h->upd_pblocks = prop.multiProcessorCount * ub;
+    }
     HIPCHK(hipDeviceSynchronize());
     *out = h;
     return AMR_OK;
@@ -1386,6 +1406,90 @@ amr_status amr_graph_launch(amr_hierarchy* h, uint32_t* parity, void* stream) {
 }  // extern "C"
 
 namespace {
+
+// Rebuild every work list for the current tile policy / z-chunk.
+void rebuild_lists(amr_hierarchy* h) {
+  for (auto g : h->graph_exec)
+    if (g) (void)hipGraphExecDestroy(g);
+  h->graph_exec[0] = h->graph_exec[1] = nullptr;
+  HIPCHK(hipFree(h->d_fitems));
+  HIPCHK(hipFree(h->d_uitems));
+  HIPCHK(hipFree(h->d_cfl));
+  h->d_fitems = nullptr;
+  h->d_uitems = nullptr;
+  h->d_cfl = nullptr;
+  h->h_fitems.clear();
+  h->h_uitems.clear();
+  h->cycle_lists.clear();
+  h->grid_lists.clear();
+  h->level0_band_lists.clear();
+  h->band2_lists.clear();
+  build_lists(h);
+}
+
+void set_launch_config(amr_hierarchy* h, int policy, int zchunk, bool persistent) {
+  if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
+  if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
+  h->persistent = persistent;
+  if (policy != h->tile_policy || zchunk != h->zchunk) {
+    h->tile_policy = policy;
+    h->zchunk = zchunk;
+    rebuild_lists(h);
+  }
+}
+
+// Milliseconds of `reps` passes over every launch cycle's batched advance,
+// reading the current buffers and writing the other ones.
+template <class T>
+double time_cycles(amr_hierarchy* h, const amr_state* Ua, const amr_state* Ub, uint32_t parity, const double* dt0,
+                   void* ws, int reps, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool timing = h->timing;
+  h->timing = false;
+  for (const LaunchList& L : h->cycle_lists) run_list<T>(h, L, Ua, Ub, parity, dt0, ws, s);  // warm-up
+  HIPCHK(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r)
+    for (const LaunchList& L : h->cycle_lists) run_list<T>(h, L, Ua, Ub, parity, dt0, ws, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  h->timing = timing;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return (double)ms;
+}
+
+template <class T>
+int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, double* dt0, void* ws, int reps,
+             amr_tune_entry* out, hipStream_t s) {
+  // valid bands on every level and a current dt0 (the next coarse step
+  // refills the bands and recomputes dt0 itself)
+  for (int l = 0; l < h->nlev; ++l) {
+    amr_state* cur = ((parity >> l) & 1u) ? Ub : Ua;
+    amr_state* par = l > 0 ? (((parity >> (l - 1)) & 1u) ? Ub : Ua) : nullptr;
+    do_fill<T>(h, l, l > 0 ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur, par, s);
+  }
+  do_dt<T>(h, Ua, Ub, parity, dt0, s);
+  const int zc[4] = {8, 16, 32, 64};
+  int best = -1, n = 0;
+  double best_ms = 0.0;
+  for (int pol = 0; pol < 2; ++pol)
+    for (int zi = 0; zi < 4; ++zi)
+      for (int per = 0; per < 2; ++per, ++n) {
+        set_launch_config(h, pol, zc[zi], per != 0);
+        const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
+        if (out) out[n] = amr_tune_entry{pol, zc[zi], per, 0, ms};
+        if (best < 0 || ms < best_ms) {
+          best = n;
+          best_ms = ms;
+        }
+      }
+  set_launch_config(h, (best >> 3) & 1, zc[(best >> 1) & 3], (best & 1) != 0);
+  return best;
+}
 
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
@@ -1735,6 +1839,39 @@ amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first
     ErrBlock z{};
     HIPCHK(hipMemcpy(h->d_err, &z, sizeof(z), hipMemcpyHostToDevice));
     return e.flags ? AMR_ESTATE : AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t persistent) {
+  try {
+    if (!h) throw Error(AMR_EINVAL, "null argument");
+    set_launch_config(h, tile_policy, zchunk, persistent != 0);
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* persistent) {
+  if (!h) return AMR_EINVAL;
+  if (tile_policy) *tile_policy = h->tile_policy;
+  if (zchunk) *zchunk = h->zchunk;
+  if (persistent) *persistent = h->persistent ? 1 : 0;
+  return AMR_OK;
+}
+
+amr_status amr_autotune(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t parity, double* dt0,
+                        void* workspace, int32_t reps, amr_tune_entry* results, int32_t* chosen, void* stream) {
+  try {
+    if (!h || !U_a || !U_b || !dt0 || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (reps < 1) throw Error(AMR_EINVAL, "reps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const int b = h->esize == 8 ? autotune<double>(h, U_a, U_b, parity, dt0, workspace, reps, results, s)
+                                : autotune<float>(h, U_a, U_b, parity, dt0, workspace, reps, results, s);
+    if (chosen) *chosen = b;
+    return AMR_OK;
   } catch (const std::exception& e) {
     return fail(e);
   }

@@ -132,3 +132,56 @@ def test_graph_replay_matches_eager_every_replay():
         for gg, gw in zip(got, ref[n]):
             for x, y in zip(gg, gw):
                 assert np.array_equal(x, y), f"replay {n}"
+
+
+@pytest.mark.parametrize("key", ["3d", "2d"])
+def test_every_launch_configuration_gives_identical_results(key):
+    """Tile policy, z-chunk and persistent vs one-block-per-item launches only
+    change how the same per-face and per-cell arithmetic is distributed:
+    two coarse steps agree bit for bit under all 16 configurations."""
+    ndim, N0, L, grids, fields = _setup(key)
+    ref = None
+    for pol in (0, 1):
+        for zc in (8, 16, 32, 64):
+            for per in (0, 1):
+                log(f"case: launch config {key} policy={pol} zchunk={zc} persistent={per}")
+                H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
+                H.set_launch_config(pol, zc, per)
+                assert A.amr_get_launch_config(H.h) == (pol, zc, per)
+                Ua, Ub = H.new_state(), H.new_state()
+                for gi, f in enumerate(fields):
+                    H.load_primitive(Ua, gi, f["prim"], f["b"])
+                par = 0
+                for _ in range(2):
+                    par = H.coarse_step(Ua, Ub, par, 0)
+                got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
+                assert H.error_flags()[0] == 0
+                if ref is None:
+                    ref = got
+                    continue
+                for gg, gw in zip(got, ref):
+                    for x, y in zip(gg, gw):
+                        assert np.array_equal(x, y)
+
+
+def test_autotune_keeps_the_state_and_the_results():
+    """The autotuner times all 16 configurations without changing what the
+    next coarse step computes."""
+    import torch
+    ndim, N0, L, grids, fields = _setup("3d")
+    ref, _, _ = amr_gpu(ndim, N0, L, grids, fields, 2)
+    H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
+    Ua, Ub = H.new_state(), H.new_state()
+    for gi, f in enumerate(fields):
+        H.load_primitive(Ua, gi, f["prim"], f["b"])
+    par = H.coarse_step(Ua, Ub, 0, 0)
+    chosen, table = H.autotune(Ua, Ub, par, reps=2)
+    log(f"autotune chose {table[chosen]}")
+    assert 0 <= chosen < 16 and all(t[3] > 0 for t in table)
+    assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
+    par = H.coarse_step(Ua, Ub, par, 0)
+    torch.cuda.synchronize()
+    got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
+    for gg, gw in zip(got, ref):
+        for x, y in zip(gg, gw):
+            assert np.array_equal(x, y)
