@@ -104,21 +104,28 @@ def single_grid_workload(args):
     return H, step, (lambda k: flops_per_step_pair * k / 2.0), info, cpu_sample, tune
 
 
-def amr_workload(args):
-    """Three-level batched AMR hierarchy, 3D FP64: base 112^3 tiled by grids
-    with even extents drawn from 8..32, each finer level covering 12.5% of its
-    parent (so every level carries about the same number of cells), band 4 so
-    each fine grid runs its 2 substeps from one fill."""
+def amr_workload(args, deep=False):
+    """Batched AMR hierarchy, 3D.  Default (3 levels, FP64): base 112^3 tiled
+    by grids with even extents drawn from 8..32, each finer level covering
+    12.5% of its parent (so every level carries about the same number of
+    cells), band 4 so each fine grid runs its 2 substeps from one fill.
+    deep (6 levels, FP32 by default): base 200^3, log-uniform extents 8..48,
+    about 3600 grids and 48M cells."""
     import numpy as np
     import torch
 
     from paper_1110_1616_amd import amr as A
     from paper_1110_1616_amd import inputs as I
 
-    N0 = (args.n0,) * 3
-    L = 3
-    grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
-    fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
+    if deep:
+        N0 = (args.n0_deep,) * 3
+        L = 6
+        grids, fields = I.deep_hierarchy(args.n0_deep, seed=5)
+    else:
+        N0 = (args.n0,) * 3
+        L = 3
+        grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
+        fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
     H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4, dtype=args.dtype)
     Ua, Ub = H.new_state(), H.new_state()
     for gi, f in enumerate(fields):
@@ -155,12 +162,13 @@ def amr_workload(args):
         with torch.cuda.stream(stream):
             return H.autotune(Ua, Ub, st["par"], reps=3)
 
+    desc = (f"{L}-level AMR hierarchy, R=2, 3D ideal MHD {args.dtype}: base {N0[0]}^3, {len(grids)} grids of even "
+            f"extents {'8..48 (log-uniform)' if deep else '8..32'} (levels {cells} cells), each level covering 12.5% "
+            f"of its parent, 4-cell extended band (2 substeps per fill), smooth Fourier-mode rho/v/A (|B| rms 0.3), "
+            f"periodic, CFL 0.4; one coarse step = fills + batched advance of R^(L-1) launch cycles "
+            f"(finest level first) + reflux/EMF fix/restriction")
     info = {
-        "workload": f"3-level AMR hierarchy, R=2, 3D ideal MHD {args.dtype}: base {args.n0}^3 tiled by {len(grids)} grids "
-                    f"of even extents 8..32 (levels {cells} cells), each level covering 12.5% of its parent, "
-                    f"4-cell extended band (2 substeps per fill), smooth Fourier-mode rho/v/A (|B| rms 0.3), "
-                    f"periodic, CFL 0.4; one coarse step = fills + batched advance of R^(L-1) launch cycles "
-                    f"(finest level first) + reflux/EMF fix/restriction",
+        "workload": desc,
         "cells": updates,  # useful cell-updates per coarse step
         "ndim": 3,
         "dtype": args.dtype,
@@ -170,14 +178,18 @@ def amr_workload(args):
 
     def cpu_sample():
         import oracle as O
-        n0s = max(8, (args.n0 // 2) // 2 * 2)
-        g2 = I.amr_hierarchy(3, (n0s,) * 3, L, seed=3, ext=(8, 32))
-        f2 = I.amr_fields(3, (n0s,) * 3, L, g2, seed=3, b_rms=0.3)
+        if deep:
+            n0s = max(8, (args.n0_deep // 2) // 2 * 2)
+            g2, f2 = I.deep_hierarchy(n0s, seed=5)
+        else:
+            n0s = max(8, (args.n0 // 2) // 2 * 2)
+            g2 = I.amr_hierarchy(3, (n0s,) * 3, L, seed=3, ext=(8, 32))
+            f2 = I.amr_fields(3, (n0s,) * 3, L, g2, seed=3, b_rms=0.3)
         c2 = [0] * L
         for (l, lo, hi) in g2:
             c2[l] += int(np.prod([hi[a] - lo[a] for a in range(3)]))
         u2 = sum(c * 2 ** l for l, c in enumerate(c2))
-        steps = args.cpu_steps
+        steps = 1 if deep else args.cpu_steps
         t = O.amr_time(3, (n0s,) * 3, L, 4, g2, f2, steps)
         return {"seconds": t, "updates": float(u2 * steps), "threads": O.max_threads(),
                 "sample": f"oracle serial level cycle on the same generator at 1/8 volume (base {n0s}^3, "
@@ -194,7 +206,7 @@ def single_workload(args):
             "flux_flops": flops, "info": info, "cpu_sample": cpu, "tune": tune}
 
 
-WORKLOADS = {"amr3": amr_workload, "single128": single_workload}
+WORKLOADS = {"amr3": amr_workload, "single128": single_workload, "deep6": lambda a: amr_workload(a, deep=True)}
 
 
 def adjoint_measure(reps=3):
@@ -251,8 +263,10 @@ def main():
     ap.add_argument("--workload", default="amr3", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--n0", type=int, default=112)
+    ap.add_argument("--n0-deep", type=int, default=200)
     ap.add_argument("--per-grid-steps", type=int, default=3)
-    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32"],
+                    help="default f64 (f32 for the deep6 workload)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -263,6 +277,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the adjoint of the 64^3 differentiation workload and print that object")
     args = ap.parse_args()
+    if args.dtype is None:
+        args.dtype = "f32" if args.workload == "deep6" else "f64"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "

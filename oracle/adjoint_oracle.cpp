@@ -414,4 +414,58 @@ int orc_ke_grad(int ndim, const int* n, double gamma, int nsteps, const double* 
   }
 }
 
+// Vector-Jacobian product of one step of the single periodic grid (band 2
+// refilled first, dt given): lam_in = (dU'/dU)^T lam_out.  U and the
+// adjoints are the eight interior arrays (cells; faces with n+1 entries
+// along their normal).  The periodic fill makes the input face n a copy of
+// face 0, so lam_in of face n is 0 and face 0 carries both.
+int orc_step_vjp(int ndim, const int* n, double gamma, double dt, const double* const* U,
+                 const double* const* lam_out, double* const* lam_in) {
+  try {
+    Layout L = lay(ndim, n, 2);
+    StepParams P = params(ndim, n, gamma);
+    g_tape.clear();
+    State<Adj> S(L), O(L);
+    std::vector<std::vector<int32_t>> ids(NVAR);
+    for (int s = 0; s < NVAR; ++s) {
+      ids[s].assign(L.fsize(s), -1);
+      for (int k = 0; k < iext(L, s, 2); ++k)
+        for (int j = 0; j < iext(L, s, 1); ++j)
+          for (int i = 0; i < iext(L, s, 0); ++i) {
+            const size_t e = L.idx(s, i, j, k);
+            const int32_t id = g_tape.push(-1, 0.0, -1, 0.0);
+            ids[s][e] = id;
+            S.f[s][e] = Adj(id, U[s][iidx(L, s, i, j, k)]);
+          }
+    }
+    fill_periodic(S);
+    step(S, O, 2, Adj(dt), P);
+    std::vector<double> adj(g_tape.a.size(), 0.0);
+    for (int s = 0; s < NVAR; ++s)
+      for (int k = 0; k < iext(L, s, 2); ++k)
+        for (int j = 0; j < iext(L, s, 1); ++j)
+          for (int i = 0; i < iext(L, s, 0); ++i) {
+            const Adj& v = O.at(s, i, j, k);
+            if (v.i >= 0) adj[v.i] += lam_out[s][iidx(L, s, i, j, k)];
+          }
+    for (int32_t t = (int32_t)g_tape.a.size() - 1; t >= 0; --t) {
+      const double at = adj[t];
+      if (at == 0.0) continue;
+      if (g_tape.a[t] >= 0) adj[g_tape.a[t]] += at * g_tape.da[t];
+      if (g_tape.b[t] >= 0) adj[g_tape.b[t]] += at * g_tape.db[t];
+    }
+    for (int s = 0; s < NVAR; ++s)
+      for (int k = 0; k < iext(L, s, 2); ++k)
+        for (int j = 0; j < iext(L, s, 1); ++j)
+          for (int i = 0; i < iext(L, s, 0); ++i)
+            lam_in[s][iidx(L, s, i, j, k)] = adj[ids[s][L.idx(s, i, j, k)]];
+    g_tape.clear();
+    return 0;
+  } catch (const std::exception& e) {
+    j_err = e.what();
+    g_tape.clear();
+    return -1;
+  }
+}
+
 }  // extern "C"

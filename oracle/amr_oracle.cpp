@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "scheme.hpp"
@@ -57,7 +58,10 @@ struct Amr {
   double gamma = 5.0 / 3.0, cfl = 0.4;
   std::vector<Grid> G;
   std::vector<std::vector<int>> lev;
-  std::vector<std::vector<int>> owner;  // dense cell -> grid map per level (-1 = none)
+  // cell -> grid lookup per level: grids listed under every 8^3-cell block
+  // they touch (levels are sparse: a deep level spans far more cells than
+  // its grids hold)
+  std::vector<std::unordered_map<int64_t, std::vector<int>>> owner;
   double dt0 = 0.0;
   bool dry = false;        // record the level order only
   std::vector<int> trace;  // levels in the order they advance
@@ -68,29 +72,42 @@ struct Amr {
   void wrap(int l, int (&p)[3]) const {
     for (int a = 0; a < nd; ++a) p[a] = pmod(p[a], N(l, a));
   }
-  size_t oidx(int l, const int (&p)[3]) const {
-    return ((size_t)p[2] * N(l, 1) + p[1]) * N(l, 0) + p[0];
+  static int64_t bkey(int bx, int by, int bz) { return ((int64_t)bz << 42) | ((int64_t)by << 21) | (int64_t)bx; }
+  // grid of level l whose interior holds the (already wrapped) cell p, or -1
+  int owner_at(int l, const int (&p)[3]) const {
+    auto it = owner[l].find(bkey(p[0] >> 3, p[1] >> 3, p[2] >> 3));
+    if (it == owner[l].end()) return -1;
+    for (int gi : it->second) {
+      const Grid& q = G[gi];
+      if (p[0] >= q.lo[0] && p[0] < q.hi[0] && p[1] >= q.lo[1] && p[1] < q.hi[1] && p[2] >= q.lo[2] &&
+          p[2] < q.hi[2])
+        return gi;
+    }
+    return -1;
   }
   // grid whose interior holds cell p of level l (periodic), or -1
   int own_cell(int l, const int (&p0)[3]) const {
     int p[3] = {p0[0], p0[1], p0[2]};
     wrap(l, p);
-    return owner[l][oidx(l, p)];
+    return owner_at(l, p);
   }
 
   void build_owner() {
     owner.assign(L, {});
     for (int l = 0; l < L; ++l) {
-      owner[l].assign((size_t)N(l, 0) * N(l, 1) * N(l, 2), -1);
       for (int gi : lev[l]) {
         const Grid& g0 = G[gi];
-        for (int k = g0.lo[2]; k < g0.hi[2]; ++k)
-          for (int j = g0.lo[1]; j < g0.hi[1]; ++j)
-            for (int i = g0.lo[0]; i < g0.hi[0]; ++i) {
-              int p[3] = {i, j, k};
-              int& o = owner[l][oidx(l, p)];
-              if (o >= 0) throw std::runtime_error("grids of one level overlap");
-              o = gi;
+        for (int bz = g0.lo[2] >> 3; bz <= (g0.hi[2] - 1) >> 3; ++bz)
+          for (int by = g0.lo[1] >> 3; by <= (g0.hi[1] - 1) >> 3; ++by)
+            for (int bx = g0.lo[0] >> 3; bx <= (g0.hi[0] - 1) >> 3; ++bx) {
+              std::vector<int>& v = owner[l][bkey(bx, by, bz)];
+              for (int o : v) {
+                const Grid& q = G[o];
+                bool meet = true;
+                for (int a = 0; a < 3; ++a) meet = meet && g0.lo[a] < q.hi[a] && q.lo[a] < g0.hi[a];
+                if (meet) throw std::runtime_error("grids of one level overlap");
+              }
+              v.push_back(gi);
             }
       }
     }
@@ -100,7 +117,7 @@ struct Amr {
   double cell_value(int l, int slot, const int (&p0)[3]) const {
     int p[3] = {p0[0], p0[1], p0[2]};
     wrap(l, p);
-    int o = owner[l][oidx(l, p)];
+    int o = owner_at(l, p);
     if (o < 0) throw std::runtime_error("cell lookup outside the level");
     const Grid& q = G[o];
     return q.S.at(slot, p[0] - q.lo[0], p[1] - q.lo[1], p[2] - q.lo[2]);
@@ -114,7 +131,7 @@ struct Amr {
       int c[3] = {p0[0], p0[1], p0[2]};
       if (side == 1) c[d] -= 1;
       wrap(l, c);
-      int w = owner[l][oidx(l, c)];
+      int w = owner_at(l, c);
       if (w < 0) continue;
       if (best < 0 || w < best) {
         best = w;
@@ -194,11 +211,28 @@ struct Amr {
     return 0.5 * (bp + bm) - add + v;
   }
 
+  // Run body(gi) for every grid of level l, grids on separate threads (each
+  // call writes only its own grid; an exception is rethrown afterwards).
+  template <class Body> void per_grid(int l, Body&& body) {
+    const std::vector<int>& gl = lev[l];
+    std::string err;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < (int)gl.size(); ++t) {
+      try {
+        body(gl[t]);
+      } catch (const std::exception& e) {
+#pragma omp critical
+        if (err.empty()) err = e.what();
+      }
+    }
+    if (!err.empty()) throw std::runtime_error(err);
+  }
+
   // ---- ghost fill of level l ----
   void fill(int l, bool full) {
     if (dry) return;
     const int ncls = nd == 3 ? 4 : 3;
-    for (int gi : lev[l]) {
+    per_grid(l, [&](int gi) {
       Grid& q = G[gi];
       const Layout& Lq = q.S.L;
       for (int cls = 0; cls < ncls; ++cls) {
@@ -242,7 +276,7 @@ struct Amr {
               }
             }
       }
-    }
+    });
   }
 
   // ---- time step ----
@@ -274,7 +308,7 @@ struct Amr {
     const int gv = l == 0 ? g : g - 2 * (k % R);
     const double dt = dt0 / ipow(R, l);
     StepParams P{gamma, {dx(l, 0), dx(l, 1), dx(l, 2)}};
-    for (int gi : lev[l]) {
+    per_grid(l, [&](int gi) {
       Grid& q = G[gi];
       State<double> out(q.S.L);
       StepCapture<double> cap;
@@ -282,7 +316,7 @@ struct Amr {
       q.S = std::move(out);
       if (l + 1 < L) q.coarse_cap = cap;
       if (l > 0) q.fine_caps.push_back(std::move(cap));
-    }
+    });
   }
 
   bool covered(int c, const int (&pc)[3]) const {
@@ -337,7 +371,7 @@ struct Amr {
           for (int x = 0; x < 3; ++x) pf[x] = x < nd ? R * p[x] : 0;
           int pw[3] = {pf[0], pf[1], pf[2]};
           wrap(c + 1, pw);
-          int o = owner[c + 1][oidx(c + 1, pw)];
+          int o = owner_at(c + 1, pw);
           if (o >= 0 && (fine_grid < 0 || o < fine_grid)) {
             fine_grid = o;
             for (int x = 0; x < 3; ++x) ew[x] = e[x] + (pw[x] - pf[x]) / R;
@@ -372,9 +406,9 @@ struct Amr {
     const double dtc = dt0 / ipow(R, c);
     const int ncs = nd == 2 ? 6 : 5;
     const int cslots[6] = {0, 1, 2, 3, 4, 7};
+    // each phase writes only the coarse grid it visits: grids run on threads
     // (1) reflux of uncovered coarse cells
-    for (int gi : lev[c]) {
-      if (g_skip & 1) break;
+    if (!(g_skip & 1)) per_grid(c, [&](int gi) {
       Grid& q = G[gi];
       for (int k = 0; k < q.S.L.n[2]; ++k)
         for (int j = 0; j < q.S.L.n[1]; ++j)
@@ -412,10 +446,9 @@ struct Amr {
                 }
               }
           }
-    }
+    });
     // (2) EMF correction of coarse faces with no covered neighbour
-    for (int gi : lev[c]) {
-      if (g_skip & 2) break;
+    if (!(g_skip & 2)) per_grid(c, [&](int gi) {
       Grid& q = G[gi];
       for (int d = 0; d < nd; ++d) {
         int lo[3], hi[3];
@@ -452,10 +485,9 @@ struct Amr {
               q.S.at(5 + d, i, j, k) -= corr;
             }
       }
-    }
+    });
     // (3) restriction of covered cells and of faces with a covered neighbour
-    for (int gi : lev[c]) {
-      if (g_skip & 4) break;
+    if (!(g_skip & 4)) per_grid(c, [&](int gi) {
       Grid& q = G[gi];
       for (int k = 0; k < q.S.L.n[2]; ++k)
         for (int j = 0; j < q.S.L.n[1]; ++j)
@@ -500,7 +532,7 @@ struct Amr {
               q.S.at(5 + d, i, j, k) = m / cnt;
             }
       }
-    }
+    });
     for (int gi : lev[f]) G[gi].fine_caps.clear();
   }
 

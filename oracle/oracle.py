@@ -369,3 +369,20 @@ def ke_branch_signature(ic, gamma, dts):
     if rc != 0:
         raise RuntimeError("oracle ke_branch_signature failed")
     return sig.value
+
+
+def step_vjp(ndim, n, gamma, dt, U, lam_out):
+    """(dU'/dU)^T lam_out for one band-2 step of the single periodic grid
+    (eight interior arrays in, eight out; see orc_step_vjp)."""
+    L = lib()
+    shapes = interior_shapes(ndim, n)
+    ku, pu = _ptrs([np.asarray(u, dtype=np.float64).reshape(sh) for u, sh in zip(U, shapes)])
+    kl, pl = _ptrs([np.asarray(x, dtype=np.float64).reshape(sh) for x, sh in zip(lam_out, shapes)])
+    out = [np.zeros(sh) for sh in shapes]
+    ko, po = _ptrs(out)
+    fn = L.orc_step_vjp
+    fn.restype = C.c_int
+    rc = fn(C.c_int(ndim), _ivec(n), C.c_double(gamma), C.c_double(dt), pu, pl, po)
+    if rc != 0:
+        raise RuntimeError(_err())
+    return ko

@@ -7,6 +7,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -431,6 +435,38 @@ void class_extent(const GridDesc& G, int ndim, int cls, int (&lo)[3], int (&hi)[
   }
 }
 
+// Run fn(i) for i in [0, n) on up to hardware_concurrency() threads; the
+// first exception thrown by any call is rethrown here.
+template <class Fn> void parallel_for(size_t n, Fn&& fn) {
+  const unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  const unsigned nt = (unsigned)std::min<size_t>(hw, n);
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nt; ++t)
+    pool.emplace_back([&]() {
+      for (;;) {
+        const size_t i = next.fetch_add(1);
+        if (i >= n) return;
+        try {
+          fn(i);
+        } catch (...) {
+          std::lock_guard<std::mutex> g(mu);
+          if (!err) err = std::current_exception();
+          next.store(n);
+          return;
+        }
+      }
+    });
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
+
 void build_fill_maps(amr_hierarchy* h) {
   const int nd = h->ndim;
   const int ncls = nd == 3 ? 4 : 3;  // 2D: Bz is a cell field, copied with the cells
@@ -447,9 +483,20 @@ void build_fill_maps(amr_hierarchy* h) {
 
   for (int l = 0; l < h->nlev; ++l) {
     const LevelIndex& LI = idx[l];
-    std::vector<CopyEntry> cp[4];
-    std::vector<ProlongEntry> pc, pf;
-    for (int gi : h->level_grids[l]) {
+    // grids are independent: worker threads build each grid's entries into
+    // its own lists, concatenated in grid order afterwards
+    struct GridMaps {
+      std::vector<CopyEntry> cp[4];
+      std::vector<ProlongEntry> pc, pf;
+    };
+    const std::vector<int>& lg = h->level_grids[l];
+    std::vector<GridMaps> per(lg.size());
+    auto one_grid = [&](size_t slot) {
+    const int gi = lg[slot];
+    std::vector<CopyEntry>(&cp)[4] = per[slot].cp;
+    std::vector<ProlongEntry>& pc = per[slot].pc;
+    std::vector<ProlongEntry>& pf = per[slot].pf;
+    {
       const GridDesc& G = h->desc[gi];
       const amr_grid& GG = h->grids[gi];
       for (int cls = 0; cls < ncls; ++cls) {
@@ -581,6 +628,16 @@ void build_fill_maps(amr_hierarchy* h) {
             }
       }
     }
+    };
+    parallel_for(lg.size(), one_grid);
+    std::vector<CopyEntry> cp[4];
+    std::vector<ProlongEntry> pc, pf;
+    for (GridMaps& m : per) {
+      for (int c = 0; c < 4; ++c) cp[c].insert(cp[c].end(), m.cp[c].begin(), m.cp[c].end());
+      pc.insert(pc.end(), m.pc.begin(), m.pc.end());
+      pf.insert(pf.end(), m.pf.begin(), m.pf.end());
+      m = GridMaps();
+    }
     std::vector<CopyEntry> all;
     int4 cls = make_int4(0, 0, 0, 0);
     for (int c = 0; c < 4; ++c) {
@@ -647,11 +704,78 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   LevelIndex CI, FI;
   CI.build(h, c);
   FI.build(h, f);
+  // covered(p) for coarse cells p of the current coarse grid's box grown by
+  // one cell: a mask filled from the fine grids' boxes (and their periodic
+  // images) before the grid's elements are visited
+  std::vector<uint8_t> mask, near;  // near: a covered cell within one cell (any direction)
+  int mlo[3] = {0, 0, 0}, mext[3] = {1, 1, 1};
+  auto near_covered = [&](const int (&pc)[3]) {
+    int64_t o = 0;
+    for (int a = 2; a >= 0; --a) o = o * mext[a] + (pc[a] - mlo[a]);
+    return near[o] != 0;
+  };
   auto covered = [&](const int (&pc)[3]) {
-    int pf[3];
-    for (int a = 0; a < 3; ++a) pf[a] = a < nd ? R * pc[a] : 0;
-    if (!FI.wrap(pf)) return false;
-    return FI.find_cell(pf) >= 0;
+    int64_t o = 0;
+    for (int a = 2; a >= 0; --a) {
+      const int x = pc[a] - mlo[a];
+      if (x < 0 || x >= mext[a]) throw Error(AMR_EINVAL, "internal: covered() outside the grid's mask");
+      o = o * mext[a] + x;
+    }
+    return mask[o] != 0;
+  };
+  auto build_mask = [&](const amr_grid& CG) {
+    for (int a = 0; a < 3; ++a) {
+      mlo[a] = a < nd ? CG.lo[a] - 1 : 0;
+      mext[a] = a < nd ? CG.hi[a] - CG.lo[a] + 2 : 1;
+    }
+    mask.assign((size_t)mext[0] * mext[1] * mext[2], 0);
+    for (int fgi : h->level_grids[f]) {
+      const amr_grid& FG = h->grids[fgi];
+      // coarse box of the fine grid (boxes are aligned to R), then every
+      // periodic image that meets the mask box
+      int flo[3], fhi[3];
+      for (int a = 0; a < 3; ++a) {
+        flo[a] = a < nd ? FG.lo[a] / R : 0;
+        fhi[a] = a < nd ? FG.hi[a] / R : 1;
+      }
+      for (int sz = -1; sz <= 1; ++sz)
+        for (int sy = -1; sy <= 1; ++sy)
+          for (int sx = -1; sx <= 1; ++sx) {
+            const int sh[3] = {sx, sy, sz};
+            int lo[3], hi[3];
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+              if (a >= nd || h->p.bc[a] != AMR_BC_PERIODIC) {
+                if (sh[a] != 0) ok = false;
+                lo[a] = std::max(flo[a], mlo[a]);
+                hi[a] = std::min(fhi[a], mlo[a] + mext[a]);
+              } else {
+                const int off = sh[a] * CI.N[a];
+                lo[a] = std::max(flo[a] + off, mlo[a]);
+                hi[a] = std::min(fhi[a] + off, mlo[a] + mext[a]);
+              }
+              ok = ok && lo[a] < hi[a];
+            }
+            if (!ok) continue;
+            for (int z = lo[2]; z < hi[2]; ++z)
+              for (int y = lo[1]; y < hi[1]; ++y)
+                for (int x = lo[0]; x < hi[0]; ++x)
+                  mask[((size_t)(z - mlo[2]) * mext[1] + (y - mlo[1])) * mext[0] + (x - mlo[0])] = 1;
+          }
+    }
+    near.assign(mask.size(), 0);
+    for (int z = 0; z < mext[2]; ++z)
+      for (int y = 0; y < mext[1]; ++y)
+        for (int x = 0; x < mext[0]; ++x) {
+          if (!mask[((size_t)z * mext[1] + y) * mext[0] + x]) continue;
+          for (int dz = (nd == 3 ? -1 : 0); dz <= (nd == 3 ? 1 : 0); ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                const int X = x + dx, Y = y + dy, Z = z + dz;
+                if (X < 0 || Y < 0 || Z < 0 || X >= mext[0] || Y >= mext[1] || Z >= mext[2]) continue;
+                near[((size_t)Z * mext[1] + Y) * mext[0] + X] = 1;
+              }
+        }
   };
   // fine grid owning fine cell p (unwrapped); shift = wrap(p) - p
   auto fine_owner = [&](const int (&p)[3], int (&shift)[3]) {
@@ -673,6 +797,7 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   for (int gi : h->level_grids[c]) {
     const GridDesc& C = h->desc[gi];
     const amr_grid& CG = h->grids[gi];
+    build_mask(CG);
     // cells: restriction or reflux
     for (int k = 0; k < C.n[2]; ++k)
       for (int j = 0; j < C.n[1]; ++j)
@@ -743,6 +868,9 @@ void build_sync_tables(amr_hierarchy* h, int f) {
             int pf[3] = {CG.lo[0] + i, CG.lo[1] + j, CG.lo[2] + k};
             int pm[3] = {pf[0], pf[1], pf[2]};
             pm[d] -= 1;
+            // faces with no covered cell within one cell of either side have
+            // nothing to restrict or correct
+            if (!near_covered(pf) && !near_covered(pm)) continue;
             const bool cu = covered(pf), cm = covered(pm);
             if (cu || cm) {
               // fine faces from the lowest-id fine grid owning a neighbour

@@ -145,8 +145,10 @@ def _face_mean_sq(ndim, b):
     return float(np.mean(s))
 
 
-def smooth_mhd(ndim, n, seed, v_rms=0.1, b_rms=0.1, rho_amp=0.1, jump=False, p0=1.0):
-    """Smooth seeded MHD state on the unit periodic box.
+def smooth_mhd(ndim, n, seed, v_rms=0.1, b_rms=0.1, rho_amp=0.1, jump=False, p0=1.0, p_amp=0.0):
+    """Smooth seeded MHD state on the unit periodic box; the pressure is p0,
+    or p0 (1 + p_amp f) with f a sum of seeded Fourier modes (drawn from a
+    stream of its own, so p_amp = 0 reproduces the other fields exactly).
 
     Returns dict(prim=[rho, vx, vy, vz, p], b=[bx, by, bz], dx=[...]) in the
     interior layout."""
@@ -166,6 +168,8 @@ def smooth_mhd(ndim, n, seed, v_rms=0.1, b_rms=0.1, rho_amp=0.1, jump=False, p0=
     vr = np.sqrt(np.mean(v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
     v = [c * (v_rms / vr) for c in v]
     p = np.full_like(rho, p0)
+    if p_amp:
+        p = p0 * (1.0 + p_amp * _Field(np.random.default_rng(seed + 7919), ndim).f_rho(x, y, z))
     b = list(curl_faces(ndim, n, fld.pot))
     scale = b_rms / np.sqrt(_face_mean_sq(ndim, b))
     b = [c * scale for c in b]
@@ -271,9 +275,17 @@ def advected_profile(N, seed=7, v=(0.37, 0.0, 0.0), p=1.0, B=(0.0, 0.0, 0.0), nd
 
 
 # ---------------------------------------------------------------- hierarchies
-def _partition(rng, length, lo_ext, hi_ext):
+def _draw_extent(rng, lo_ext, hi_ext, log_uniform):
+    if log_uniform:
+        e = float(np.exp(rng.uniform(np.log(lo_ext), np.log(hi_ext))))
+        return int(min(hi_ext, max(lo_ext, round(e / 2) * 2)))
+    return int(rng.integers(lo_ext // 2, hi_ext // 2 + 1)) * 2
+
+
+def _partition(rng, length, lo_ext, hi_ext, log_uniform=False):
     """Split `length` cells into consecutive even segments with extents in
-    [lo_ext, hi_ext] (seeded); the last segment absorbs the remainder."""
+    [lo_ext, hi_ext] (seeded, uniform or log-uniform); the last segment
+    absorbs the remainder."""
     segs = []
     left = length
     while left > 0:
@@ -287,7 +299,7 @@ def _partition(rng, length, lo_ext, hi_ext):
                     a = (t // 2) // 2 * 2
                     segs += [a, t - a]
             break
-        e = int(rng.integers(lo_ext // 2, hi_ext // 2 + 1)) * 2
+        e = _draw_extent(rng, lo_ext, hi_ext, log_uniform)
         if left - e < lo_ext and left - e != 0:
             e = left - lo_ext if left - lo_ext <= hi_ext else e
         segs.append(e)
@@ -295,10 +307,10 @@ def _partition(rng, length, lo_ext, hi_ext):
     return segs
 
 
-def _tile_box(rng, lo, hi, ndim, lo_ext, hi_ext):
+def _tile_box(rng, lo, hi, ndim, lo_ext, hi_ext, log_uniform=False):
     axes = []
     for a in range(ndim):
-        segs = _partition(rng, hi[a] - lo[a], lo_ext, hi_ext)
+        segs = _partition(rng, hi[a] - lo[a], lo_ext, hi_ext, log_uniform)
         starts = np.cumsum([0] + segs[:-1]) + lo[a]
         axes.append(list(zip(starts, segs)))
     boxes = []
@@ -314,16 +326,18 @@ def _tile_box(rng, lo, hi, ndim, lo_ext, hi_ext):
     return boxes
 
 
-def amr_hierarchy(ndim, N0, nlevels, seed, ext=(8, 32), fill_fraction=0.125, ghost=4, max_boxes=4, ratio=2):
+def amr_hierarchy(ndim, N0, nlevels, seed, ext=(8, 32), fill_fraction=0.125, ghost=4, max_boxes=4, ratio=2,
+                  log_uniform=False):
     """Seeded nested hierarchy.  Level 0 tiles the periodic domain; each
     level l >= 1 covers about `fill_fraction` of the volume of level l-1 with
     1..max_boxes boxes placed inside the level-(l-1) boxes shrunk by the
     nesting buffer (ghost/R + 1 coarse cells); every box is tiled by grids
-    whose extents are even and drawn from [ext[0], ext[1]].  Returns a list of
-    (level, lo, hi) in level-l cell indices."""
+    whose extents are even and drawn from [ext[0], ext[1]] (uniformly, or
+    log-uniformly when log_uniform).  Returns a list of (level, lo, hi) in
+    level-l cell indices."""
     rng = np.random.default_rng(seed)
     N0 = tuple(int(v) for v in N0)[:ndim]
-    grids = [(0, lo, hi) for lo, hi in _tile_box(rng, (0,) * ndim, N0, ndim, ext[0], ext[1])]
+    grids = [(0, lo, hi) for lo, hi in _tile_box(rng, (0,) * ndim, N0, ndim, ext[0], ext[1], log_uniform)]
     parents = [((0,) * ndim, N0)]  # boxes of the previous level (level units)
     buf = ghost // ratio + 1
     for l in range(1, nlevels):
@@ -359,7 +373,7 @@ def amr_hierarchy(ndim, N0, nlevels, seed, ext=(8, 32), fill_fraction=0.125, gho
             if ok:
                 boxes.append((tuple(lo), tuple(hi)))
         for (blo, bhi) in boxes:
-            grids += [(l, lo, hi) for lo, hi in _tile_box(rng, blo, bhi, ndim, ext[0], ext[1])]
+            grids += [(l, lo, hi) for lo, hi in _tile_box(rng, blo, bhi, ndim, ext[0], ext[1], log_uniform)]
         parents = boxes
     return grids
 
@@ -373,16 +387,19 @@ def _edge_mean_factor(k, h_fine, r):
     return np.sin(r * d / 2) / (r * np.sin(d / 2))
 
 
-def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1, ratio=2):
+def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1, ratio=2, p_amp=0.0):
     """Per-grid primitive data of a hierarchy, sampled from one set of smooth
     random fields.  Cells take point values at their centres.  The vector
     potential of every level is the mean of the finest level's edge samples
     along each edge (a closed form per Fourier mode), so face B of every
     level is the discrete curl of consistent potentials: a coarse face equals
     the mean of the finest faces on it, up to rounding.  Amplitudes are set
-    from level 0.  Returns a list of dict(prim=[...], b=[...]) per grid."""
+    from level 0.  The pressure is 1, or 1 + p_amp f with f smooth modes of a
+    stream of their own.  Returns a list of dict(prim=[...], b=[...]) per
+    grid."""
     rng = np.random.default_rng(seed)
     fld = _Field(rng, ndim)
+    pfld = _Field(np.random.default_rng(seed + 7919), ndim) if p_amp else None
     N0 = tuple(int(v) for v in N0)[:ndim]
     Lf = nlevels - 1
 
@@ -411,6 +428,7 @@ def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1
         x, y, z = _grid(xs, ys, zs)
         rho = 1.0 + rho_amp * fld.f_rho(x, y, z)
         v = fld.curl_psi(x, y, z)
+        p = 1.0 + p_amp * pfld.f_rho(x, y, z) if p_amp else np.ones_like(rho)
         pot = level_pot(l)
 
         def wp(a, count, off):
@@ -439,12 +457,12 @@ def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1
             bx = ((az[1:, :] - az[:-1, :]) / h[1])[None]
             by = (-(az[:, 1:] - az[:, :-1]) / h[0])[None]
             bz = ((ay[:, 1:] - ay[:, :-1]) / h[0] - (ax[1:, :] - ax[:-1, :]) / h[1])[None]
-        return rho, v, [bx, by, bz]
+        return rho, v, [bx, by, bz], p
 
     raw = [sample_grid(l, lo, hi) for (l, lo, hi) in grids]
     # amplitudes from level 0 (which tiles the domain)
     vs, bs, nc = 0.0, 0.0, 0
-    for (l, lo, hi), (rho, v, b) in zip(grids, raw):
+    for (l, lo, hi), (rho, v, b, _p) in zip(grids, raw):
         if l != 0:
             continue
         vs += float(np.sum(v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
@@ -453,8 +471,8 @@ def amr_fields(ndim, N0, nlevels, grids, seed, v_rms=0.1, b_rms=0.3, rho_amp=0.1
     vscale = v_rms / np.sqrt(vs / nc)
     bscale = b_rms / np.sqrt(bs / nc)
     out = []
-    for (l, lo, hi), (rho, v, b) in zip(grids, raw):
-        prim = [rho, v[0] * vscale, v[1] * vscale, v[2] * vscale, np.ones_like(rho)]
+    for (l, lo, hi), (rho, v, b, p) in zip(grids, raw):
+        prim = [rho, v[0] * vscale, v[1] * vscale, v[2] * vscale, p]
         out.append({"prim": prim, "b": [c * bscale for c in b]})
     return out
 
@@ -532,3 +550,13 @@ def smooth_directions(n, count, seed, kmax=2, nmodes=4, scale=0.1):
             d.append(f)
         out.append(d)
     return out
+
+
+def deep_hierarchy(N0=200, seed=5, p_amp=0.0):
+    """The deep-hierarchy workload: 3D, 6 levels, R = 2, each level covering
+    12.5% of its parent (so every level holds about N0^3 cells), grids with
+    log-uniform even extents in [8, 48], band 4.  N0 = 100 is its 1/8-volume
+    subvolume.  Returns (grids, fields)."""
+    grids = amr_hierarchy(3, (N0,) * 3, 6, seed=seed, ext=(8, 48), log_uniform=True)
+    fields = amr_fields(3, (N0,) * 3, 6, grids, seed=seed, b_rms=0.3, p_amp=p_amp)
+    return grids, fields
