@@ -245,7 +245,8 @@ amr_status amr_graph_launch(amr_hierarchy* h, uint32_t* parity, void* stream);
  *     faces [0, n] along their normal and [0, n) across); band entries are
  *     ignored.  On exit, the adjoint of the state before the first step: own
  *     elements hold it (band images folded into the elements they copy),
- *     band elements are zero; elements of other levels are untouched.
+ *     band elements are zero; elements outside the level's grid boxes are
+ *     untouched.
  *   workspace: device memory of amr_adjoint_workspace() bytes (the forward
  *     recompute of the segment's states lives there).
  * The cost is one forward pass (nsteps - 1 steps) plus nsteps reverse steps. */

@@ -1760,8 +1760,19 @@ void adjoint_run(amr_hierarchy* h, int level, int nsteps, const double* dts, con
   buf.e0 = t.e0;
   amr_state other;
   for (int q = 0; q < 8; ++q) other.f[q] = base + a.off_lam + q * arr;
+  // ping-pong so that the last reverse step writes lam itself (its kernels
+  // write only the level's grid boxes, so other levels' entries stay): with
+  // an odd step count the seed is first copied into the workspace buffer
   const amr_state* Lp = lam;
   const amr_state* Lo = &other;
+  if (nsteps % 2 == 1) {
+    const int64_t es = (int64_t)sizeof(T);
+    for (int q = 0; q < 8; ++q)
+      HIPCHK(hipMemcpyAsync((char*)other.f[q] + t.e0 * es, (const char*)lam->f[q] + t.e0 * es, (t.e1 - t.e0) * es,
+                            hipMemcpyDeviceToDevice, s));
+    Lp = &other;
+    Lo = lam;
+  }
   const Phys ph = phys(h);
   for (int k = nsteps - 1; k >= 0; --k) {
     amr_state sk = state_at(k);
@@ -1770,10 +1781,6 @@ void adjoint_run(amr_hierarchy* h, int level, int nsteps, const double* dts, con
     HIPCHK(hipGetLastError());
     std::swap(Lp, Lo);
   }
-  if (Lp != lam)
-    for (int q = 0; q < 8; ++q)
-      HIPCHK(hipMemcpyAsync((char*)lam->f[q] + t.e0 * (int64_t)sizeof(T), (const char*)Lp->f[q] + t.e0 * (int64_t)sizeof(T),
-                            (t.e1 - t.e0) * (int64_t)sizeof(T), hipMemcpyDeviceToDevice, s));
 }
 
 // Frozen-branch advance: pairs (base, perturbed) in workspace, the same
