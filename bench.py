@@ -35,6 +35,31 @@ FLOPS_HLLD = 367
 GAMMA = 5.0 / 3.0
 
 
+def kernel_source_digest():
+    """sha256 over the sources that define the flux kernel's memory traffic."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp"):
+        with open(os.path.join(ROOT, "paper_1110_1616_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, dtype):
+    """HBM bytes per flux-kernel launch from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what
+    the counter reads for a copy of known size), or None if there is none or
+    the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_flux_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_digest() or rec.get("dtype") != dtype:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def flux_kernel_flops(ndim, n, gv):
     """Algorithmic flops of one flux-kernel launch over a grid with interior n
     (per axis) advanced from valid band gv."""
@@ -271,6 +296,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch-config", default=None,
+                    help="tile_policy,zchunk,persistent: set this launch configuration instead of autotuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")
@@ -290,11 +317,12 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
+        # an elementwise kernel that reads and writes exactly N bytes each
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     if args.adjoint_only:
@@ -321,7 +349,11 @@ def main():
         W["eager"]()
     torch.cuda.synchronize()
     tuned = None
-    if W.get("tune") and not args.no_autotune:
+    if args.launch_config:
+        pol, zc, per = (int(v) for v in args.launch_config.split(","))
+        H.set_launch_config(pol, zc, per)
+        tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "persistent": per}, "set_by": "--launch-config"}
+    elif W.get("tune") and not args.no_autotune:
         chosen, table = W["tune"]()
         torch.cuda.synchronize()
         tuned = {"chosen": {"tile_policy": table[chosen][0], "zchunk": table[chosen][1],
@@ -381,7 +413,8 @@ def main():
         "config": {"workload": info["workload"], "grids": info["grids"],
                    "useful_cell_updates_per_step": info["cells"], "parallelism": "single GPU"},
         "roofline": {"kernel": "k_flux", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload, info["dtype"]),
                      "avg_launch_ms": flux_ms / max(nl, 1), "launches": nl},
         "kernels_ms_per_step": {"k_flux": flux_ms / args.steps, "k_update": upd_ms / args.steps},
         "eager_value": updates / (eager_ms / 1e3),
