@@ -297,7 +297,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch-config", default=None,
-                    help="tile_policy,zchunk,persistent: set this launch configuration instead of autotuning")
+                    help="tile_policy,zchunk,launch_mode: set this launch configuration instead of autotuning "
+                         "(launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")
@@ -352,12 +353,12 @@ def main():
     if args.launch_config:
         pol, zc, per = (int(v) for v in args.launch_config.split(","))
         H.set_launch_config(pol, zc, per)
-        tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "persistent": per}, "set_by": "--launch-config"}
+        tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "launch_mode": per}, "set_by": "--launch-config"}
     elif W.get("tune") and not args.no_autotune:
         chosen, table = W["tune"]()
         torch.cuda.synchronize()
         tuned = {"chosen": {"tile_policy": table[chosen][0], "zchunk": table[chosen][1],
-                            "persistent": table[chosen][2]},
+                            "launch_mode": table[chosen][2]},
                  "candidates_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
         for _ in range(2):
             W["eager"]()

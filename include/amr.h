@@ -290,29 +290,35 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
 /* Launch configuration of the batched advance.  tile_policy 0: 16 x 16
  * thread tiles; 1: per grid and band, the tile width in [4, 64] (256 threads
  * per tile) that launches the fewest tiles over the grid.  zchunk: planes per
- * work item along z (3D).  persistent 0: one block per work item; 1: a fixed
+ * work item along z (3D).  launch_mode bit 0: persistent launches (a fixed
  * grid of resident blocks popping the launch's item list from a device
- * queue (one atomic per item, list order = finest level first), the queue
- * resetting itself at the end of each launch.  Results do not depend on the
- * configuration (bitwise).  Changing tile_policy or zchunk rebuilds the work
- * lists and drops captured graphs.  Default: 1, 16, 0. */
-amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t persistent);
-amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* persistent);
+ * queue, one atomic per item, list order = finest level first; the queue
+ * resets itself at the end of each launch), else one block per work item;
+ * bit 1: the item list is cut into 8 contiguous chunks, one per XCD
+ * (workgroups reach the XCDs round-robin, so chunk c runs on XCD c and
+ * neighbouring tiles share its L2; persistent blocks drain their own chunk
+ * first, then the others).  Results do not depend on the configuration
+ * (bitwise).  Changing tile_policy or zchunk rebuilds the work lists and
+ * drops captured graphs.  Default: 1, 16, 0. */
+amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
+amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
+
+#define AMR_TUNE_CANDIDATES 32
 
 typedef struct {
-  int32_t tile_policy, zchunk, persistent, pad;
+  int32_t tile_policy, zchunk, launch_mode, pad;
   double ms; /* reps passes over every launch cycle's batched advance */
 } amr_tune_entry;
 
 /* Autotuner of the batched advance: fills every level's band (FULL, coarse
  * to fine) and computes dt0 (both redone by the next coarse step), then
- * times each of the 16 configurations (tile_policy x zchunk in {8, 16, 32,
- * 64} x persistent) over `reps` passes of every launch cycle's batched
- * advance, reading each level's current buffer (parity) and writing the
- * other one, and keeps the fastest.  The state the next amr_coarse_step()
- * reads is not changed.  results: host array of 16 entries or NULL;
- * *chosen (or NULL): index of the kept entry.  Synchronises the stream;
- * drops captured graphs. */
+ * times each of the AMR_TUNE_CANDIDATES configurations (tile_policy x zchunk
+ * in {8, 16, 32, 64} x launch_mode in [0, 3]) over `reps` passes of every
+ * launch cycle's batched advance, reading each level's current buffer
+ * (parity) and writing the other one, and keeps the fastest.  The state the
+ * next amr_coarse_step() reads is not changed.  results: host array of
+ * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
+ * entry.  Synchronises the stream; drops captured graphs. */
 amr_status amr_autotune(amr_hierarchy* h, amr_state* U_a, amr_state* U_b, uint32_t parity, double* dt0,
                         void* workspace, int32_t reps, amr_tune_entry* results, int32_t* chosen, void* stream);
 

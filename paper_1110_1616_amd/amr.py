@@ -40,7 +40,7 @@ class amr_state(C.Structure):
 
 
 class amr_tune_entry(C.Structure):
-    _fields_ = [("tile_policy", C.c_int32), ("zchunk", C.c_int32), ("persistent", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("tile_policy", C.c_int32), ("zchunk", C.c_int32), ("launch_mode", C.c_int32), ("pad", C.c_int32),
                 ("ms", C.c_double)]
 
 
@@ -252,8 +252,9 @@ def amr_advance_frozen(h, level, dts, Ubase, Upert, ws):
            "amr_advance_frozen")
 
 
-def amr_set_launch_config(h, tile_policy, zchunk, persistent):
-    _check(lib().amr_set_launch_config(h, tile_policy, zchunk, int(bool(persistent))), "amr_set_launch_config")
+def amr_set_launch_config(h, tile_policy, zchunk, launch_mode):
+    """launch_mode bit 0: persistent queue; bit 1: one item chunk per XCD."""
+    _check(lib().amr_set_launch_config(h, tile_policy, zchunk, int(launch_mode)), "amr_set_launch_config")
 
 
 def amr_get_launch_config(h):
@@ -262,13 +263,16 @@ def amr_get_launch_config(h):
     return a.value, b.value, c.value
 
 
+TUNE_CANDIDATES = 32
+
+
 def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):
-    """Returns (chosen index, [(tile_policy, zchunk, persistent, ms), ...])."""
-    res = (amr_tune_entry * 16)()
+    """Returns (chosen index, [(tile_policy, zchunk, launch_mode, ms), ...])."""
+    res = (amr_tune_entry * TUNE_CANDIDATES)()
     ch = C.c_int32()
     _check(lib().amr_autotune(h, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws), reps, res, C.byref(ch),
                               _stream()), "amr_autotune")
-    return ch.value, [(r.tile_policy, r.zchunk, r.persistent, r.ms) for r in res]
+    return ch.value, [(r.tile_policy, r.zchunk, r.launch_mode, r.ms) for r in res]
 
 
 def amr_get_error_flags(h):
@@ -401,8 +405,8 @@ class Hierarchy:
     def autotune(self, Ua, Ub, parity, reps=3):
         return amr_autotune(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, reps)
 
-    def set_launch_config(self, tile_policy, zchunk, persistent):
-        amr_set_launch_config(self.h, tile_policy, zchunk, persistent)
+    def set_launch_config(self, tile_policy, zchunk, launch_mode):
+        amr_set_launch_config(self.h, tile_policy, zchunk, launch_mode)
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua

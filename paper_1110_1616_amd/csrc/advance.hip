@@ -39,24 +39,54 @@ __device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& 
 // Next work item of this block.  Grid-stride launches take blockIdx.x,
 // blockIdx.x + gridDim.x, ...; persistent launches (a fixed number of blocks)
 // pop the shared queue, one atomic per item, in list order (finest level
-// first), so blocks that draw cheap items come back for more.  Returns -1
+// first), so blocks that draw cheap items come back for more.  With `xcd`
+// the list is cut into 8 contiguous chunks, one per XCD (workgroups are
+// dispatched to the 8 XCDs round-robin, so block b runs on XCD b mod 8):
+// neighbouring tiles, which share halo data, then run under one L2.  A
+// one-block-per-item launch maps block b to item (b mod 8) C + b / 8; a
+// persistent block pops its own chunk first, then the others.  Returns -1
 // when the list is exhausted.
 template <bool PERSIST>
-__device__ __forceinline__ int next_item(int& cursor, int nitems, WorkQueue* q, int* s_it) {
+__device__ __forceinline__ int next_item(int& cursor, int nitems, WorkQueue* q, int* s_it, int* s_c, bool xcd) {
+  const int C = (nitems + 7) >> 3;
   if (!PERSIST) {
+    if (xcd) {
+      if (cursor < 0) return -1;
+      const int b = cursor;
+      cursor = -1;
+      const int it = (b & 7) * C + (b >> 3);
+      return it < nitems ? it : -1;
+    }
     const int it = cursor;
     cursor += gridDim.x;
     return it < nitems ? it : -1;
   }
-  if (threadIdx.x == 0) *s_it = (int)atomicAdd(&q->head, 1u);
+  if (threadIdx.x == 0) {
+    int res = -1;
+    if (!xcd) {
+      const unsigned i = atomicAdd(&q->head[0], 1u);
+      if ((int)i < nitems) res = (int)i;
+    } else {
+      while (res < 0 && *s_c < 8) {
+        const int c = (int)((blockIdx.x + *s_c) & 7);
+        const int lo = c * C, len = min(C, nitems - lo);
+        if (len > 0) {
+          const unsigned i = atomicAdd(&q->head[c], 1u);
+          if ((int)i < len) res = lo + (int)i;
+        }
+        if (res < 0) ++*s_c;  // this chunk is drained: move to the next
+      }
+    }
+    *s_it = res;
+  }
   __syncthreads();
   const int it = *s_it;
   __syncthreads();
-  return it < nitems ? it : -1;
+  return it;
 }
 
 // Persistent launches leave the queue ready for the next one: the last block
-// to finish resets both counters (every other block has made its final pop
+// to finish resets the counters (every other block has made its final pop
 // before it counts itself done).
 template <bool PERSIST>
 __device__ __forceinline__ void retire(WorkQueue* q) {
@@ -65,7 +95,7 @@ __device__ __forceinline__ void retire(WorkQueue* q) {
     __threadfence();
     const unsigned d = atomicAdd(&q->done, 1u);
     if (d == gridDim.x - 1) {
-      atomicExch(&q->head, 0u);
+      for (int c = 0; c < 8; ++c) atomicExch(&q->head[c], 0u);
       atomicExch(&q->done, 0u);
     }
   }
@@ -75,9 +105,10 @@ template <class T, int NDIM, bool PERSIST>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                               DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err,
-                                              WorkQueue* q) {
+                                              WorkQueue* q, bool xcd) {
   __shared__ T sW[8][kMaxPlane];
-  __shared__ int s_it;
+  __shared__ int s_it, s_c;
+  if (threadIdx.x == 0) s_c = 0;
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
 
@@ -87,7 +118,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 
   int cursor = blockIdx.x;
   for (;;) {
-    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it);
+    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it, &s_c, xcd);
     if (it < 0) break;
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -232,12 +263,14 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 template <class T, int NDIM, bool PERSIST>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
                                                 int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
-                                                DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, WorkQueue* q) {
-  __shared__ int s_it;
+                                                DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, WorkQueue* q,
+                                                bool xcd) {
+  __shared__ int s_it, s_c;
+  if (threadIdx.x == 0) s_c = 0;
   const int tid = threadIdx.x;
   int cursor = blockIdx.x;
   for (;;) {
-    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it);
+    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it, &s_c, xcd);
     if (it < 0) break;
     const UpdItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -327,40 +360,40 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 hipStream_t s) {
+                 bool xcd, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
-  const dim3 grid(per ? std::min(pblocks, nitems) : nitems), block(256);
+  const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
   if (ndim == 3) {
     if (per)
-      hipLaunchKernelGGL((k_flux<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+      hipLaunchKernelGGL((k_flux<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
     else
-      hipLaunchKernelGGL((k_flux<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+      hipLaunchKernelGGL((k_flux<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
   } else {
     if (per)
-      hipLaunchKernelGGL((k_flux<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+      hipLaunchKernelGGL((k_flux<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
     else
-      hipLaunchKernelGGL((k_flux<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q);
+      hipLaunchKernelGGL((k_flux<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
   }
 }
 
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   hipStream_t s) {
+                   bool xcd, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
-  const dim3 grid(per ? std::min(pblocks, nitems) : nitems), block(256);
+  const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
   if (ndim == 3) {
     if (per)
-      hipLaunchKernelGGL((k_update<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+      hipLaunchKernelGGL((k_update<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
     else
-      hipLaunchKernelGGL((k_update<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+      hipLaunchKernelGGL((k_update<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
   } else {
     if (per)
-      hipLaunchKernelGGL((k_update<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+      hipLaunchKernelGGL((k_update<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
     else
-      hipLaunchKernelGGL((k_update<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q);
+      hipLaunchKernelGGL((k_update<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
   }
 }
 
@@ -381,9 +414,9 @@ void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_
 
 #define AMR_ADV_INST(T)                                                                                             \
   template void launch_flux<T>(int, const GridDesc*, const FluxItem*, int, DevState<T>, DevState<T>, uint32_t,     \
-                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, hipStream_t);          \
+                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, hipStream_t);    \
   template void launch_update<T>(int, const GridDesc*, const UpdItem*, int, DevState<T>, DevState<T>, uint32_t,   \
-                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, hipStream_t);
+                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, bool, hipStream_t);
 AMR_ADV_INST(float)
 AMR_ADV_INST(double)
 // frozen-branch instances (finite-difference verification of the adjoint)

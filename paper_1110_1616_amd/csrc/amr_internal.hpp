@@ -78,23 +78,25 @@ struct ErrBlock {
 // Counters of the persistent launches' shared work queue (device memory,
 // zero between launches: each persistent launch resets them as it ends).
 struct WorkQueue {
-  unsigned head;
+  unsigned head[8];  // one counter per XCD chunk (only [0] without chunks)
   unsigned done;
+  unsigned pad[7];
 };
 
 // Host-side launchers (defined in the .hip translation units).
 // Level l of a grid reads its state from S1 if bit l of `parity` is set,
 // else from S0; the update writes the other one.
 // pblocks > 0 (with a queue): a persistent launch of pblocks blocks that pop
-// the items; else one block per item.
+// the items; else one block per item.  xcd: items in 8 contiguous chunks, one
+// per XCD.
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 hipStream_t s);
+                 bool xcd, hipStream_t s);
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   hipStream_t s);
+                   bool xcd, hipStream_t s);
 template <class T> void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu);
 
 }  // namespace amr

@@ -128,6 +128,7 @@ struct amr_hierarchy {
   int zchunk = 16;
   int tile_policy = 1;  // 0: 16 x 16 tiles; 1: per-grid width with the fewest tiles
   bool persistent = false;     // persistent launches popping d_queue, or one block per item
+  bool xcd_chunks = false;     // item lists cut into one contiguous chunk per XCD
   WorkQueue* d_queue = nullptr;
   int flux_pblocks = 0, upd_pblocks = 0;  // persistent grid sizes (resident blocks on the device)
 
@@ -1043,11 +1044,11 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
-                 h->d_queue, h->persistent ? h->flux_pblocks : 0, s);
+                 h->d_queue, h->persistent ? h->flux_pblocks : 0, h->xcd_chunks, s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
   launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, h->d_queue,
-                   h->persistent ? h->upd_pblocks : 0, s);
+                   h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, s);
   HIPCHK(hipGetLastError());
   if (timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
@@ -1555,10 +1556,12 @@ void rebuild_lists(amr_hierarchy* h) {
   build_lists(h);
 }
 
-void set_launch_config(amr_hierarchy* h, int policy, int zchunk, bool persistent) {
+void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
   if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
-  h->persistent = persistent;
+  if (mode < 0 || mode > 3) throw Error(AMR_EINVAL, "launch mode must be in [0, 3]");
+  h->persistent = (mode & 1) != 0;
+  h->xcd_chunks = (mode & 2) != 0;
   if (policy != h->tile_policy || zchunk != h->zchunk) {
     h->tile_policy = policy;
     h->zchunk = zchunk;
@@ -1606,16 +1609,16 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
   double best_ms = 0.0;
   for (int pol = 0; pol < 2; ++pol)
     for (int zi = 0; zi < 4; ++zi)
-      for (int per = 0; per < 2; ++per, ++n) {
-        set_launch_config(h, pol, zc[zi], per != 0);
+      for (int mode = 0; mode < 4; ++mode, ++n) {
+        set_launch_config(h, pol, zc[zi], mode);
         const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
-        if (out) out[n] = amr_tune_entry{pol, zc[zi], per, 0, ms};
+        if (out) out[n] = amr_tune_entry{pol, zc[zi], mode, 0, ms};
         if (best < 0 || ms < best_ms) {
           best = n;
           best_ms = ms;
         }
       }
-  set_launch_config(h, (best >> 3) & 1, zc[(best >> 1) & 3], (best & 1) != 0);
+  set_launch_config(h, (best >> 4) & 1, zc[(best >> 2) & 3], best & 3);
   return best;
 }
 
@@ -1979,21 +1982,21 @@ amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first
   }
 }
 
-amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t persistent) {
+amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode) {
   try {
     if (!h) throw Error(AMR_EINVAL, "null argument");
-    set_launch_config(h, tile_policy, zchunk, persistent != 0);
+    set_launch_config(h, tile_policy, zchunk, launch_mode);
     return AMR_OK;
   } catch (const std::exception& e) {
     return fail(e);
   }
 }
 
-amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* persistent) {
+amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode) {
   if (!h) return AMR_EINVAL;
   if (tile_policy) *tile_policy = h->tile_policy;
   if (zchunk) *zchunk = h->zchunk;
-  if (persistent) *persistent = h->persistent ? 1 : 0;
+  if (launch_mode) *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0);
   return AMR_OK;
 }
 

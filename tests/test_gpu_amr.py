@@ -136,15 +136,16 @@ def test_graph_replay_matches_eager_every_replay():
 
 @pytest.mark.parametrize("key", ["3d", "2d"])
 def test_every_launch_configuration_gives_identical_results(key):
-    """Tile policy, z-chunk and persistent vs one-block-per-item launches only
-    change how the same per-face and per-cell arithmetic is distributed:
-    two coarse steps agree bit for bit under all 16 configurations."""
+    """Tile policy, z-chunk, persistent vs one-block-per-item launches and XCD
+    chunking only change how the same per-face and per-cell arithmetic is
+    distributed: two coarse steps agree bit for bit under all 32
+    configurations."""
     ndim, N0, L, grids, fields = _setup(key)
     ref = None
     for pol in (0, 1):
         for zc in (8, 16, 32, 64):
-            for per in (0, 1):
-                log(f"case: launch config {key} policy={pol} zchunk={zc} persistent={per}")
+            for per in (0, 1, 2, 3):
+                log(f"case: launch config {key} policy={pol} zchunk={zc} mode={per}")
                 H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
                 H.set_launch_config(pol, zc, per)
                 assert A.amr_get_launch_config(H.h) == (pol, zc, per)
@@ -165,7 +166,7 @@ def test_every_launch_configuration_gives_identical_results(key):
 
 
 def test_autotune_keeps_the_state_and_the_results():
-    """The autotuner times all 16 configurations without changing what the
+    """The autotuner times all 32 configurations without changing what the
     next coarse step computes."""
     import torch
     ndim, N0, L, grids, fields = _setup("3d")
@@ -177,7 +178,7 @@ def test_autotune_keeps_the_state_and_the_results():
     par = H.coarse_step(Ua, Ub, 0, 0)
     chosen, table = H.autotune(Ua, Ub, par, reps=2)
     log(f"autotune chose {table[chosen]}")
-    assert 0 <= chosen < 16 and all(t[3] > 0 for t in table)
+    assert 0 <= chosen < A.TUNE_CANDIDATES and all(t[3] > 0 for t in table)
     assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
     par = H.coarse_step(Ua, Ub, par, 0)
     torch.cuda.synchronize()
