@@ -35,6 +35,17 @@ FLOPS_HLLD = 367
 GAMMA = 5.0 / 3.0
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_source_digest():
     """sha256 over the sources that define the flux kernel's memory traffic."""
     import hashlib
@@ -215,10 +226,17 @@ def amr_workload(args, deep=False):
             c2[l] += int(np.prod([hi[a] - lo[a] for a in range(3)]))
         u2 = sum(c * 2 ** l for l, c in enumerate(c2))
         steps = 1 if deep else args.cpu_steps
+        nthr = O.max_threads()
         t = O.amr_time(3, (n0s,) * 3, L, 4, g2, f2, steps)
-        return {"seconds": t, "updates": float(u2 * steps), "threads": O.max_threads(),
+        # the same sample's first coarse step on one core
+        O.set_threads(1)
+        t1 = O.amr_time(3, (n0s,) * 3, L, 4, g2, f2, 1)
+        O.set_threads(nthr)
+        return {"seconds": t, "updates": float(u2 * steps), "threads": nthr, "seconds_1core": t1,
+                "updates_1core": float(u2),
                 "sample": f"oracle serial level cycle on the same generator at 1/8 volume (base {n0s}^3, "
-                          f"{len(g2)} grids), {steps} coarse steps"}
+                          f"{len(g2)} grids), {steps} coarse steps (1 on one core); OpenMP over the grids of a "
+                          f"level"}
 
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
             "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
@@ -432,7 +450,10 @@ def main():
     if not args.no_cpu_baseline:
         cs = W["cpu_sample"]()
         out["cpu_baseline"] = {"value": cs["updates"] / cs["seconds"], "unit": "cell-updates/s",
-                               "cores": cs["threads"], "kind": "oracle", "sample": cs["sample"]}
+                               "cores": cs["threads"], "kind": "oracle", "sample": cs["sample"],
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        if "seconds_1core" in cs:
+            out["cpu_baseline"]["value_1core"] = cs["updates_1core"] / cs["seconds_1core"]
     print(json.dumps(out), flush=True)
 
 
