@@ -160,6 +160,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     const int kend = NDIM == 3 ? item.z1 : 1;
 
     T wprev[8], wcur[8], wnext[8], wring[8];
+    T fbcur[3][2], fbnext[3][2];  // face fields of the current / next plane's cell
     T zcarry[7];
 #pragma unroll
     for (int q = 0; q < 8; ++q) { wprev[q] = T(1); wcur[q] = T(1); wnext[q] = T(1); wring[q] = T(1); }
@@ -168,7 +169,9 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 
     // prologue: W(kstart-1) own (3D), W(kstart) own + ring into LDS
     if (NDIM == 3 && ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart - 1), ix.sy, ix.sz, gm1, wprev);
-    if (ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart), ix.sy, ix.sz, gm1, wcur);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fbcur[d][0] = fbcur[d][1] = fbnext[d][0] = fbnext[d][1] = T(0);
+    if (ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, kstart), ix.sy, ix.sz, gm1, wcur, fbcur);
     if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, kstart), ix.sy, ix.sz, gm1, wring);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 
     for (int k = kstart; k < kend; ++k) {
       if (NDIM == 3) {
-        if (ook) load_prim<T, NDIM>(U, ix(cx, cy, k + 1), ix.sy, ix.sz, gm1, wnext);
+        if (ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, k + 1), ix.sy, ix.sz, gm1, wnext, fbnext);
         if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, k + 1), ix.sy, ix.sz, gm1, wring);
       }
       Pred<T, NDIM> pr;
@@ -194,19 +197,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
         }
         if ((wcur[0] <= T(0)) || (wcur[4] <= T(0))) flag_bad(err, ix(cx, cy, k));
         const int64_t e = ix(cx, cy, k);
-        T fb[3][2];
-        fb[0][0] = U.f[5][e];
-        fb[0][1] = U.f[5][e + 1];
-        fb[1][0] = U.f[6][e];
-        fb[1][1] = U.f[6][e + ix.sy];
-        if (NDIM == 3) {
-          fb[2][0] = U.f[7][e];
-          fb[2][1] = U.f[7][e + ix.sz];
-        } else {
-          fb[2][0] = T(0);
-          fb[2][1] = T(0);
-        }
-        bool ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fb, hdt, idx, gam, pr);
+        bool ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fbcur, hdt, idx, gam, pr);
         if (!ok) flag_bad(err, e);
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
@@ -222,7 +213,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           T l[7];
 #pragma unroll
           for (int q = 0; q < 7; ++q) l[q] = sX[q][tid - 1];
-          hlld7(l, pr.m[0], U.f[5][e], gam, f);
+          hlld7(l, pr.m[0], fbcur[0][0], gam, f);
 #pragma unroll
           for (int q = 0; q < 7; ++q) F.f[0][q][e] = f[q];
         }
@@ -230,12 +221,12 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           T l[7];
 #pragma unroll
           for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - tw];
-          hlld7(l, pr.m[1], U.f[6][e], gam, f);
+          hlld7(l, pr.m[1], fbcur[1][0], gam, f);
 #pragma unroll
           for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
         }
         if (NDIM == 3 && k > cl) {
-          hlld7(zcarry, pr.m[2], U.f[7][e], gam, f);
+          hlld7(zcarry, pr.m[2], fbcur[2][0], gam, f);
 #pragma unroll
           for (int q = 0; q < 7; ++q) F.f[2][q][e] = f[q];
         }
@@ -252,6 +243,11 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           if (tid < nring) sW[q][rey * kW + rex] = wring[q];
           wprev[q] = wcur[q];
           wcur[q] = wnext[q];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          fbcur[d][0] = fbnext[d][0];
+          fbcur[d][1] = fbnext[d][1];
         }
         __syncthreads();
       }

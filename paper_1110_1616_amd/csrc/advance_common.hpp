@@ -38,6 +38,36 @@ __device__ __forceinline__ void load_prim(const DevState<T>& U, int64_t e, int32
   to_primitive(u, w, gm1);
 }
 
+// load_prim that also returns the cell's six face fields (low/high along
+// x, y, z; zero along z in 2D), which the predictor needs as the normal B of
+// its face states.
+template <class T, int NDIM>
+__device__ __forceinline__ void load_prim_faces(const DevState<T>& U, int64_t e, int32_t sy, int32_t sz, T gm1,
+                                                T (&w)[8], T (&fb)[3][2]) {
+  T u[8];
+  u[0] = U.f[0][e];
+  u[1] = U.f[1][e];
+  u[2] = U.f[2][e];
+  u[3] = U.f[3][e];
+  u[4] = U.f[4][e];
+  fb[0][0] = U.f[5][e];
+  fb[0][1] = U.f[5][e + 1];
+  fb[1][0] = U.f[6][e];
+  fb[1][1] = U.f[6][e + sy];
+  u[5] = T(0.5) * (fb[0][0] + fb[0][1]);
+  u[6] = T(0.5) * (fb[1][0] + fb[1][1]);
+  if (NDIM == 3) {
+    fb[2][0] = U.f[7][e];
+    fb[2][1] = U.f[7][e + sz];
+    u[7] = T(0.5) * (fb[2][0] + fb[2][1]);
+  } else {
+    fb[2][0] = T(0);
+    fb[2][1] = T(0);
+    u[7] = U.f[7][e];
+  }
+  to_primitive(u, w, gm1);
+}
+
 __device__ __forceinline__ void flag_bad(ErrBlock* err, int64_t e) {
   unsigned old = atomicOr(&err->flags, 1u);
   if ((old & 1u) == 0u) atomicExch((unsigned long long*)&err->first_bad, (unsigned long long)e);
