@@ -622,6 +622,105 @@ void store_grid(const Amr& A, int gi, double* const* out) {
         for (int i = 0; i < iext(L, s, 0); ++i) out[s][iidx(L, s, i, j, k)] = q.S.at(s, i, j, k);
 }
 
+// ---- (O)verlap: a new iteration of grids from the previous one ----
+// The paper's successive iterations of grids on a level and the transfer of
+// the fluid variables from the previous iteration (Sec. 2; the O of the level
+// cycle, Sec. 4).  Levels are taken coarse to fine.  A new cell lying in an
+// old same-level interior takes that value, otherwise it is prolonged from
+// the new level l-1 (minmod-linear, as in the band fill).  A new face lying
+// in or on an old same-level interior takes that value (lowest old grid id);
+// otherwise a face on a coarse face is reconstructed on that face (as in the
+// band fill) and the faces inside an uncovered coarse cell are the mean of
+// the two opposite boundary faces corrected by the smallest change that makes
+// every fine cell divergence-free: with r(c) the divergence of fine cell c
+// under those means, p solves the cell-graph Laplacian L p = r (edge weights
+// 1/dx_d^2, solved in its eigenbasis, the 2^nd sign patterns
+// chi_s(c) = (-1)^(s.c), eigenvalue 2 sum_{d in s} 1/dx_d^2), and the face
+// between cells c (low side) and c + e_d loses (p(c) - p(c + e_d)) / dx_d.
+void project_cell_faces(Amr& A, int l, Grid& q, const int (&pc)[3]) {
+  const int nd = A.nd;
+  const int nc = 1 << nd;
+  double dx[3];
+  for (int d = 0; d < 3; ++d) dx[d] = A.dx(l, d);
+  // local index of fine cell c (bits along x, y, z) and its face along d
+  auto face = [&](int d, int c, int up) -> double& {
+    int x[3] = {0, 0, 0};
+    for (int a = 0; a < nd; ++a) x[a] = 2 * pc[a] + ((c >> a) & 1) - q.lo[a];
+    x[d] += up;
+    return q.S.at(5 + d, x[0], x[1], x[2]);
+  };
+  // interior faces: mean of the boundary faces in line with them
+  for (int d = 0; d < nd; ++d)
+    for (int c = 0; c < nc; ++c) {
+      if ((c >> d) & 1) continue;  // the face above cell c (bit d = 0) is interior
+      const int c1 = c | (1 << d);
+      face(d, c, 1) = 0.5 * (face(d, c, 0) + face(d, c1, 1));
+    }
+  double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < nc; ++c)
+    for (int d = 0; d < nd; ++d) r[c] += (face(d, c, 1) - face(d, c, 0)) / dx[d];
+  double pot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int sgn = 1; sgn < nc; ++sgn) {
+    double lam = 0.0, dot = 0.0;
+    for (int d = 0; d < nd; ++d)
+      if ((sgn >> d) & 1) lam += 2.0 / (dx[d] * dx[d]);
+    for (int c = 0; c < nc; ++c) dot += (__builtin_popcount(sgn & c) & 1 ? -1.0 : 1.0) * r[c];
+    for (int c = 0; c < nc; ++c) pot[c] += (__builtin_popcount(sgn & c) & 1 ? -1.0 : 1.0) * dot / (nc * lam);
+  }
+  for (int d = 0; d < nd; ++d)
+    for (int c = 0; c < nc; ++c) {
+      if ((c >> d) & 1) continue;
+      const int c1 = c | (1 << d);
+      face(d, c, 1) -= (pot[c] - pot[c1]) / dx[d];
+    }
+}
+
+void overlap(const Amr& Ao, Amr& An) {
+  const int nd = An.nd;
+  const int ns = nd == 2 ? 6 : 5;
+  const int slots[6] = {0, 1, 2, 3, 4, 7};
+  for (int l = 0; l < An.L; ++l) {
+    for (int gi : An.lev[l]) {
+      Grid& q = An.G[gi];
+      const Layout& Lq = q.S.L;
+      for (int k = 0; k < Lq.n[2]; ++k)
+        for (int j = 0; j < Lq.n[1]; ++j)
+          for (int i = 0; i < Lq.n[0]; ++i) {
+            int p[3] = {q.lo[0] + i, q.lo[1] + j, q.lo[2] + k};
+            const bool old = Ao.own_cell(l, p) >= 0;
+            if (!old && l == 0) throw std::runtime_error("overlap: level-0 cell not covered by the old level 0");
+            for (int t = 0; t < ns; ++t)
+              q.S.at(slots[t], i, j, k) = old ? Ao.cell_value(l, slots[t], p) : An.prolong_cell(l, slots[t], p);
+          }
+      for (int d = 0; d < nd; ++d)
+        for (int k = 0; k < Lq.n[2] + (d == 2 ? 1 : 0); ++k)
+          for (int j = 0; j < Lq.n[1] + (d == 1 ? 1 : 0); ++j)
+            for (int i = 0; i < Lq.n[0] + (d == 0 ? 1 : 0); ++i) {
+              int p[3] = {q.lo[0] + i, q.lo[1] + j, q.lo[2] + k};
+              int o, loc[3];
+              if (Ao.face_owner(l, d, p, o, loc)) {
+                q.S.at(5 + d, i, j, k) = Ao.G[o].S.at(5 + d, loc[0], loc[1], loc[2]);
+              } else if (l == 0) {
+                throw std::runtime_error("overlap: level-0 face not covered by the old level 0");
+              } else if (pmod(p[d], 2) == 0) {
+                q.S.at(5 + d, i, j, k) = An.prolong_face(l, d, p);
+              }
+              // faces inside an uncovered coarse cell: projected below
+            }
+      if (l == 0) continue;
+      // uncovered coarse cells under the grid (new grids are R-aligned)
+      for (int ck = q.lo[2] / 2; ck < (nd == 3 ? q.hi[2] / 2 : 1); ++ck)
+        for (int cj = q.lo[1] / 2; cj < q.hi[1] / 2; ++cj)
+          for (int ci = q.lo[0] / 2; ci < q.hi[0] / 2; ++ci) {
+            int f[3] = {2 * ci, 2 * cj, nd == 3 ? 2 * ck : 0};
+            if (Ao.own_cell(l, f) >= 0) continue;
+            int pc[3] = {ci, cj, ck};
+            project_cell_faces(An, l, q, pc);
+          }
+    }
+  }
+}
+
 }  // namespace
 }  // namespace orc
 
@@ -715,6 +814,74 @@ int orc_amr_fill(int ndim, const int* N0, int nlev, int g, const double* dx0, in
     for (int i = 0; i < ngrids; ++i)
       for (int s = 0; s < NVAR; ++s)
         std::memcpy(banded[8 * i + s], A->G[i].S.f[s].data(), A->G[i].S.f[s].size() * sizeof(double));
+    delete A;
+    return 0;
+  } catch (const std::exception& e) {
+    a_err = e.what();
+    delete A;
+    return -1;
+  }
+}
+
+
+// (O)verlap from the previous iteration of grids (old_desc, conserved
+// interiors old_cons: nold*8 interior-layout pointers) into a new iteration
+// (new_desc; new_cons receives nnew*8 interior-layout arrays).  Both
+// hierarchies share the domain, ratio and level count; new boxes are aligned
+// to multiples of R.  Returns 0 or -1 (orc_amr_last_error()).
+int orc_amr_overlap(int ndim, const int* N0, int nlev, int g, const double* dx0, int nold, const int* old_desc,
+                    const double* const* old_cons, int nnew, const int* new_desc, double* const* new_cons) {
+  Amr* Ao = nullptr;
+  Amr* An = nullptr;
+  try {
+    Ao = make_amr(ndim, N0, nlev, g, 5.0 / 3.0, 0.4, dx0, nold, old_desc);
+    An = make_amr(ndim, N0, nlev, g, 5.0 / 3.0, 0.4, dx0, nnew, new_desc);
+    for (int i = 0; i < nnew; ++i)
+      for (int a = 0; a < ndim; ++a)
+        if (An->G[i].level > 0 && (pmod(An->G[i].lo[a], 2) || pmod(An->G[i].hi[a], 2)))
+          throw std::runtime_error("overlap: new box not aligned to the refinement ratio");
+    for (int i = 0; i < nold; ++i) {
+      Grid& q = Ao->G[i];
+      const Layout& L = q.S.L;
+      for (int s = 0; s < NVAR; ++s)
+        for (int k = 0; k < iext(L, s, 2); ++k)
+          for (int j = 0; j < iext(L, s, 1); ++j)
+            for (int ii = 0; ii < iext(L, s, 0); ++ii) q.S.at(s, ii, j, k) = old_cons[8 * i + s][iidx(L, s, ii, j, k)];
+    }
+    overlap(*Ao, *An);
+    for (int i = 0; i < nnew; ++i) store_grid(*An, i, new_cons + 8 * i);
+    delete Ao;
+    delete An;
+    return 0;
+  } catch (const std::exception& e) {
+    a_err = e.what();
+    delete Ao;
+    delete An;
+    return -1;
+  }
+}
+
+// Like orc_amr_run, with conserved interiors given directly (cons: ngrids*8
+// interior-layout pointers) instead of primitives.
+int orc_amr_run_cons(int ndim, const int* N0, int nlev, int g, double gamma, double cfl, const double* dx0,
+                     int ngrids, const int* desc, const double* const* cons, int ncoarse, const double* dts_in,
+                     double* const* out, double* dts_out) {
+  Amr* A = nullptr;
+  try {
+    A = make_amr(ndim, N0, nlev, g, gamma, cfl, dx0, ngrids, desc);
+    for (int i = 0; i < ngrids; ++i) {
+      Grid& q = A->G[i];
+      const Layout& L = q.S.L;
+      for (int s = 0; s < NVAR; ++s)
+        for (int k = 0; k < iext(L, s, 2); ++k)
+          for (int j = 0; j < iext(L, s, 1); ++j)
+            for (int ii = 0; ii < iext(L, s, 0); ++ii) q.S.at(s, ii, j, k) = cons[8 * i + s][iidx(L, s, ii, j, k)];
+    }
+    for (int s = 0; s < ncoarse; ++s) {
+      A->coarse_step(dts_in ? dts_in[s] : -1.0);
+      if (dts_out) dts_out[s] = A->dt0;
+    }
+    for (int i = 0; i < ngrids; ++i) store_grid(*A, i, out + 8 * i);
     delete A;
     return 0;
   } catch (const std::exception& e) {

@@ -297,6 +297,53 @@ def amr_fill(ndim, N0, nlev, g, grids, cons, level, full):
     return [k2[8 * i:8 * i + 8] for i in range(len(grids))]
 
 
+def amr_run_cons(ndim, N0, nlev, g, grids, cons, ncoarse, gamma=5.0 / 3.0, cfl=0.4, dts=None):
+    """amr_run with conserved interiors given directly (per grid 8
+    interior-layout arrays)."""
+    L = lib()
+    L.orc_amr_last_error.restype = C.c_char_p
+    desc = _grid_desc(ndim, grids)
+    k1, pc = _ptrs([a for c in cons for a in c])
+    outs = []
+    for (l, lo, hi) in grids:
+        outs.append([np.zeros(s) for s in interior_shapes(ndim, _gshape(ndim, lo, hi))])
+    k3, po = _ptrs([a for o in outs for a in o])
+    dts_out = np.zeros(max(ncoarse, 1))
+    pin = None
+    if dts is not None:
+        dts_in = np.ascontiguousarray(dts, dtype=np.float64)
+        pin = dts_in.ctypes.data_as(_dp)
+    dx0 = [1.0 / N0[a] for a in range(ndim)]
+    rc = L.orc_amr_run_cons(C.c_int(ndim), _ivec(N0), C.c_int(nlev), C.c_int(g), C.c_double(gamma),
+                            C.c_double(cfl), _dvec(dx0), C.c_int(len(grids)), desc.ctypes.data_as(_ip), pc,
+                            C.c_int(ncoarse), pin, po, dts_out.ctypes.data_as(_dp))
+    if rc != 0:
+        raise RuntimeError("oracle amr_run_cons: " + L.orc_amr_last_error().decode())
+    return [k3[8 * i:8 * i + 8] for i in range(len(grids))], dts_out[:ncoarse]
+
+
+def amr_overlap(ndim, N0, nlev, g, old_grids, old_cons, new_grids):
+    """(O)verlap: conserved interiors of a new iteration of grids from the
+    previous iteration (Sec. 2 and 4 of the paper).  Returns per new grid 8
+    interior-layout arrays."""
+    L = lib()
+    L.orc_amr_last_error.restype = C.c_char_p
+    d_old = _grid_desc(ndim, old_grids)
+    d_new = _grid_desc(ndim, new_grids)
+    k1, pc = _ptrs([a for c in old_cons for a in c])
+    outs = []
+    for (l, lo, hi) in new_grids:
+        outs.append([np.zeros(s) for s in interior_shapes(ndim, _gshape(ndim, lo, hi))])
+    k2, po = _ptrs([a for o in outs for a in o])
+    dx0 = [1.0 / N0[a] for a in range(ndim)]
+    rc = L.orc_amr_overlap(C.c_int(ndim), _ivec(N0), C.c_int(nlev), C.c_int(g), _dvec(dx0),
+                           C.c_int(len(old_grids)), d_old.ctypes.data_as(_ip), pc, C.c_int(len(new_grids)),
+                           d_new.ctypes.data_as(_ip), po)
+    if rc != 0:
+        raise RuntimeError("oracle amr_overlap: " + L.orc_amr_last_error().decode())
+    return [k2[8 * i:8 * i + 8] for i in range(len(new_grids))]
+
+
 def amr_level_order(nlev):
     """Levels in the order the serial cycle advances them in one coarse step."""
     buf = (C.c_int * 4096)()
