@@ -344,6 +344,91 @@ amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first
  * forward-mode dual number.  `which` out of range or ntrials < 1 returns -1. */
 double amr_selfcheck_adjoint(int32_t which, int32_t ntrials, uint64_t seed);
 
+/* ---- regridding and the (O)verlap transfer ----
+ * The mesh is adaptive: each level has successive iterations of grids, and
+ * the fluid variables move from the previous iteration to the current one
+ * (Sec. 2, AMR Algorithm; the (O) of the level cycle, Sec. 4).  The paper
+ * fixes neither the refinement criterion nor the clustering; this library
+ * flags on the relative centred density jump and clusters with the
+ * algorithm of Berger & Rigoutsos (1991, IEEE Trans. Syst. Man Cybern. 21,
+ * 1278).  A regrid of level l+1 is: amr_regrid() on the current hierarchy
+ * (new grid list), amr_create() on that list, then amr_overlap() level by
+ * level, coarse to fine, into the new hierarchy's state. */
+
+typedef struct {
+  double theta;      /* flag when |rho(c+e_d) - rho(c-e_d)| > theta (rho(c+e_d) + rho(c-e_d)) for some d */
+  double efficiency; /* accept a box when flagged cells >= efficiency * volume, in (0, 1] */
+  int32_t buffer;    /* flags grow by this many cells in every direction (>= 0) */
+  int32_t max_box;   /* largest extent of a new box, in level-l cells (>= 1) */
+} amr_regrid_params;
+
+/* Number of interior cells of the grids of `level` (the flag layout). */
+amr_status amr_level_cells(const amr_hierarchy* h, int32_t level, int64_t* ncells);
+
+/* Host-only Berger-Rigoutsos clustering (the rule amr_regrid() applies) of
+ * the set cells of mask (host, extent[0] * extent[1] (* extent[2]) bytes, x
+ * fastest) inside [0, extent); admissible (host, same layout, may be NULL
+ * for all) marks the cells a box may contain.  boxes (host, capacity x 6
+ * int32): lo[3], hi[3] per box in emission order; *nout = the count
+ * (AMR_EINVAL with *nout set when capacity is too small).  Needs no GPU. */
+amr_status amr_cluster_boxes(int32_t ndim, const int32_t* extent, const uint8_t* mask, const uint8_t* admissible,
+                             double efficiency, int32_t max_box, int32_t* boxes, int32_t capacity, int32_t* nout);
+
+/* Refinement flags of `level`.  First fills the level's band from its
+ * current data: at level 0 a same-level fill of U_level; above it a
+ * same-level fill of the parent (U_parent, level-1's current data; only its
+ * band changes) and a full fill of U_level.  Then flags[c] = 1 for every
+ * interior cell c with |rho(c+e_d) - rho(c-e_d)| > theta (rho(c+e_d) +
+ * rho(c-e_d)) along some active axis d (FP64 arithmetic), else 0.  flags:
+ * device buffer of amr_level_cells() bytes; grids of the level in increasing
+ * index, each grid's interior cells x fastest, then y, then z.  Stream
+ * ordered, no synchronisation. */
+amr_status amr_flag_cells(amr_hierarchy* h, int32_t level, amr_state* U_level, amr_state* U_parent, double theta,
+                          uint8_t* flags, void* stream);
+
+/* New grid list with level+1 re-clustered (0 <= level <= nlevels - 2).
+ * Flags of `level` as amr_flag_cells() (band fills included), copied to the
+ * host (synchronises the stream); grown by params->buffer cells (periodic
+ * axes wrap); kept only where nestable: a level cell c is nestable when the
+ * cube c + [-b, b]^ndim, b = g/R + 1, lies in the union of the level's
+ * interiors, the proper-nesting rule amr_create() checks.  The grids of
+ * level+2 are kept: the level cells under each of them grown by b
+ * level-(level+1) cells are added (AMR_EINVAL if one is not nestable).
+ * Berger-Rigoutsos clustering of those cells over the level's index space:
+ * a box is shrunk to its cells and accepted when cells >= efficiency *
+ * volume, every extent <= max_box and every cell nestable, or when it is a
+ * single cell; otherwise it is cut at a hole of the signature (axes by
+ * decreasing extent, the hole nearest the middle), else at the strongest
+ * sign change of the signature's second difference, else halved along the
+ * longest axis; boxes are emitted depth first, low part first.  out
+ * (host, capacity records): the grids of levels <= level in their order,
+ * the new level+1 boxes (times R), then the grids of levels >= level+2 in
+ * their order; *nout = the count (AMR_EINVAL with *nout set when capacity
+ * is too small).  AMR_EUNSUPPORTED when the level's grids span more than
+ * 2^28 cells of index space. */
+amr_status amr_regrid(amr_hierarchy* h, int32_t level, amr_state* U_level, amr_state* U_parent,
+                      const amr_regrid_params* params, amr_grid* out, int32_t capacity, int32_t* nout, void* stream);
+
+/* (O)verlap of one level of a new iteration of grids (h_new) from the
+ * previous iteration (h_old, same domain, spacing, boundaries, level count,
+ * ratio and dtype).  U_old: the old level's current data; U_new receives the
+ * new level; U_new_parent: the new level-1 data, already transferred and with
+ * its band filled (NULL at level 0).  Every interior element of every new
+ * grid: a cell lying in an old interior of the same level, or a face lying in
+ * or on one (lowest old grid index), is copied; otherwise (level > 0) cells
+ * are prolonged from the parent as in the band fill, faces on coarse faces
+ * are reconstructed on the face as in the band fill, and the faces inside
+ * each prolonged coarse cell start as the mean of the two boundary faces in
+ * line with them and take the smallest correction (least squares) that makes
+ * every fine cell of the coarse cell divergence-free.  Then the level's band
+ * is filled from the new hierarchy (same-level at level 0, full above), so
+ * the next level can be transferred and flags taken.  Call it for levels 0,
+ * 1, ... in order.  Builds the maps on the host and synchronises the stream
+ * before it returns.  AMR_EINVAL: a level-0 element the old level 0 does not
+ * cover, a box not aligned to R, or a new cell without a parent. */
+amr_status amr_overlap(amr_hierarchy* h_new, int32_t level, amr_state* U_new, amr_state* U_new_parent,
+                       const amr_hierarchy* h_old, const amr_state* U_old, void* stream);
+
 /* Text of the last error on this host thread. */
 const char* amr_last_error(void);
 const char* amr_strerror(amr_status s);

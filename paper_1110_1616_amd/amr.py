@@ -44,6 +44,10 @@ class amr_tune_entry(C.Structure):
                 ("ms", C.c_double)]
 
 
+class amr_regrid_params(C.Structure):
+    _fields_ = [("theta", C.c_double), ("efficiency", C.c_double), ("buffer", C.c_int32), ("max_box", C.c_int32)]
+
+
 class AmrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -96,6 +100,16 @@ def lib():
         L.amr_graph_launch.argtypes = [_VP, C.POINTER(C.c_uint32), _VP]
         L.amr_set_kernel_timing.argtypes = [_VP, C.c_int32]
         L.amr_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.amr_cluster_boxes.argtypes = [C.c_int32, C.POINTER(C.c_int32), _VP, _VP, C.c_double, C.c_int32,
+                                        C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        L.amr_level_cells.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int64)]
+        L.amr_flag_cells.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), C.c_double, _VP,
+                                     _VP]
+        L.amr_regrid.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state),
+                                 C.POINTER(amr_regrid_params), C.POINTER(amr_grid), C.c_int32,
+                                 C.POINTER(C.c_int32), _VP]
+        L.amr_overlap.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), _VP,
+                                  C.POINTER(amr_state), _VP]
         _LIB = L
     return _LIB
 
@@ -305,6 +319,60 @@ def amr_kernel_times(h):
     return a.value, b.value, n.value
 
 
+def amr_cluster_boxes(mask, admissible=None, efficiency=0.7, max_box=16):
+    """Host clustering of a numpy bool mask indexed [x, y(, z)]; returns
+    [(lo, hi)] tuples of ndim entries in emission order."""
+    nd = mask.ndim
+    ext = (C.c_int32 * 3)(*(list(mask.shape) + [1] * (3 - nd)))
+    m = np.ascontiguousarray(np.transpose(mask).astype(np.uint8))  # x fastest
+    a = None if admissible is None else np.ascontiguousarray(np.transpose(admissible).astype(np.uint8))
+    n = C.c_int32(0)
+    cap = 4096
+    while True:
+        out = (C.c_int32 * (6 * cap))()
+        rc = lib().amr_cluster_boxes(nd, ext, m.ctypes.data_as(C.c_void_p),
+                                     None if a is None else a.ctypes.data_as(C.c_void_p), float(efficiency),
+                                     int(max_box), out, cap, C.byref(n))
+        if rc == AMR_EINVAL and n.value > cap:
+            cap = n.value
+            continue
+        _check(rc, "amr_cluster_boxes")
+        return [(tuple(out[6 * q:6 * q + nd]), tuple(out[6 * q + 3:6 * q + 3 + nd])) for q in range(n.value)]
+
+
+def amr_level_cells(h, level):
+    n = C.c_int64()
+    _check(lib().amr_level_cells(h, level, C.byref(n)), "amr_level_cells")
+    return n.value
+
+
+def amr_flag_cells(h, level, U_level, U_parent, theta, flags):
+    up = C.byref(U_parent) if U_parent is not None else None
+    _check(lib().amr_flag_cells(h, level, C.byref(U_level), up, float(theta), _ptr(flags), _stream()),
+           "amr_flag_cells")
+
+
+def amr_regrid(h, level, U_level, U_parent, theta, efficiency=0.7, buffer=1, max_box=16):
+    """New grid list [(level, lo3, hi3)] with level+1 re-clustered."""
+    rp = amr_regrid_params(float(theta), float(efficiency), int(buffer), int(max_box))
+    up = C.byref(U_parent) if U_parent is not None else None
+    n = C.c_int32(0)
+    cap = 1024
+    while True:
+        arr = (amr_grid * cap)()
+        rc = lib().amr_regrid(h, level, C.byref(U_level), up, C.byref(rp), arr, cap, C.byref(n), _stream())
+        if rc == AMR_EINVAL and n.value > cap:
+            cap = n.value
+            continue
+        _check(rc, "amr_regrid")
+        return [(g.level, tuple(g.lo), tuple(g.hi)) for g in arr[:n.value]]
+
+
+def amr_overlap(h_new, level, U_new, U_new_parent, h_old, U_old):
+    up = C.byref(U_new_parent) if U_new_parent is not None else None
+    _check(lib().amr_overlap(h_new, level, C.byref(U_new), up, h_old, C.byref(U_old), _stream()), "amr_overlap")
+
+
 # ----------------------------------------------------------- convenience
 class State:
     """Eight device pools (torch tensors) of one hierarchy state."""
@@ -410,6 +478,28 @@ class Hierarchy:
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua
+
+    def flags(self, level, U, Up, theta):
+        """Refinement flags of `level` (uint8 tensor in the flag layout)."""
+        t = self.torch
+        f = t.zeros(max(amr_level_cells(self.h, level), 1), dtype=t.uint8, device=self.device)
+        amr_flag_cells(self.h, level, U.c, Up.c if Up is not None else None, theta, f)
+        return f
+
+    def regrid(self, level, U, Up, theta, efficiency=0.7, buffer=1, max_box=16):
+        """Grid list of the next iteration with level+1 re-clustered (lo/hi
+        trimmed to ndim entries)."""
+        g = amr_regrid(self.h, level, U.c, Up.c if Up is not None else None, theta, efficiency, buffer, max_box)
+        return [(l, tuple(lo[:self.ndim]), tuple(hi[:self.ndim])) for (l, lo, hi) in g]
+
+    def overlap_from(self, old, old_states):
+        """(O)verlap of every level, coarse to fine, from hierarchy `old`
+        (old_states[l]: the State holding level l's current data) into a new
+        State of this hierarchy, which is returned."""
+        U = self.new_state()
+        for l in range(self.nlevels):
+            amr_overlap(self.h, l, U.c, U.c if l > 0 else None, old.h, old_states[l].c)
+        return U
 
     def error_flags(self):
         return amr_get_error_flags(self.h)
