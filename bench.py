@@ -238,9 +238,53 @@ def amr_workload(args, deep=False):
                           f"{len(g2)} grids), {steps} coarse steps (1 on one core); OpenMP over the grids of a "
                           f"level"}
 
+    def regrid_measure():
+        """One regrid of level 2 from the level-1 flags of the current state:
+        flags + clustering (amr_regrid), the new hierarchy's tables
+        (amr_create + workspace), the (O)verlap of every level, then the
+        coarse-step time of the regridded hierarchy (eager, batched)."""
+        par = st["par"]
+        cur = [H.current(Ua, Ub, par, l) for l in range(L)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            new = H.regrid(1, cur[1], cur[0], args.regrid_theta, efficiency=args.regrid_eff,
+                           max_box=args.regrid_max_box)
+        t1 = time.perf_counter()
+        Hn = A.Hierarchy(3, N0, new, nlevels=L, ghost=4, dtype=args.dtype)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            Un = Hn.overlap_from(H, cur)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        Vn = Hn.new_state()
+        p2 = 0
+        with torch.cuda.stream(stream):
+            p2 = Hn.coarse_step(Un, Vn, p2, 0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                p2 = Hn.coarse_step(Un, Vn, p2, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if Hn.error_flags()[0]:
+            raise RuntimeError("non-physical state after the regrid")
+        c2 = [0] * L
+        for (l, lo, hi) in new:
+            c2[l] += int(np.prod([hi[a] - lo[a] for a in range(3)]))
+        return {"level": 2, "theta": args.regrid_theta, "efficiency": args.regrid_eff,
+                "max_box": args.regrid_max_box, "grids_before": len(grids), "grids_after": len(new),
+                "level_cells_after": c2, "regrid_ms": (t1 - t0) * 1e3, "create_ms": (t2 - t1) * 1e3,
+                "overlap_ms": (t3 - t2) * 1e3,
+                "coarse_step_ms_after": e0.elapsed_time(e1) / 3,
+                "cell_updates_per_s_after": sum(c * 2 ** l for l, c in enumerate(c2)) / (e0.elapsed_time(e1) / 3e3)}
+
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
             "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
-            "tune": tune}
+            "tune": tune, "regrid": None if deep else regrid_measure}
 
 
 def single_workload(args):
@@ -314,6 +358,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-regrid", action="store_true", help="skip the regrid measurement (3-level workload)")
+    ap.add_argument("--regrid-theta", type=float, default=0.03,
+                    help="flag threshold of the measured regrid (relative centred density jump)")
+    ap.add_argument("--regrid-eff", type=float, default=0.5, help="clustering efficiency of the measured regrid")
+    ap.add_argument("--regrid-max-box", type=int, default=32,
+                    help="largest box extent of the measured regrid, in level-1 cells")
     ap.add_argument("--launch-config", default=None,
                     help="tile_policy,zchunk,launch_mode: set this launch configuration instead of autotuning "
                          "(launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD)")
@@ -445,6 +495,8 @@ def main():
         out["batched_over_per_grid"] = value / per_grid
     if tuned is not None:
         out["autotune"] = tuned
+    if W.get("regrid") and not args.no_regrid:
+        out["regrid"] = W["regrid"]()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_measure()
     if not args.no_cpu_baseline:

@@ -2157,11 +2157,13 @@ struct NestMap {
     // the region spans the periodic axis)
     nest = cov;
     std::vector<uint8_t> tmp;
+    std::vector<int> pre;
     for (int a = 0; a < nd; ++a) {
       tmp = nest;
       const int n = ext[a];
       const int64_t stride = a == 0 ? 1 : (a == 1 ? (int64_t)ext[0] : (int64_t)ext[0] * ext[1]);
       int o1 = (a + 1) % 3, o2 = (a + 2) % 3;
+      pre.assign(n + 2 * buf + 1, 0);
       for (int v = 0; v < ext[o2]; ++v)
         for (int u = 0; u < ext[o1]; ++u) {
           int x[3];
@@ -2169,19 +2171,16 @@ struct NestMap {
           x[o1] = lo[o1] + u;
           x[o2] = lo[o2] + v;
           const int64_t base = at(x);
-          for (int i = 0; i < n; ++i) {
-            bool ok = true;
-            for (int s = -buf; s <= buf && ok; ++s) {
-              int q = i + s;
-              if (full[a]) q = posmod(q, n);
-              else if (q < 0 || q >= n) {
-                ok = false;
-                break;
-              }
-              ok = tmp[base + q * stride] != 0;
-            }
-            nest[base + i * stride] = ok ? 1 : 0;
+          // prefix counts of uncovered cells over the line extended by buf
+          // on both sides (wrapped on a full periodic axis, else uncovered)
+          for (int j = 0; j < n + 2 * buf; ++j) {
+            int q = j - buf;
+            int unc;
+            if (full[a]) unc = tmp[base + (int64_t)posmod(q, n) * stride] ? 0 : 1;
+            else unc = (q < 0 || q >= n) ? 1 : (tmp[base + (int64_t)q * stride] ? 0 : 1);
+            pre[j + 1] = pre[j] + unc;
           }
+          for (int i = 0; i < n; ++i) nest[base + (int64_t)i * stride] = (pre[i + 2 * buf + 1] - pre[i]) == 0 ? 1 : 0;
         }
     }
   }
@@ -2219,8 +2218,7 @@ std::vector<amr_grid> do_regrid(amr_hierarchy* h, int level, amr_state* Ul, amr_
   const int buf = h->g / R + 1;
   NestMap nm;
   nm.build(h, level, buf, buf + rp->buffer + 1);
-  auto key = [&](const int (&x)[3]) { return ((int64_t)x[2] * nm.N[1] + x[1]) * nm.N[0] + x[0]; };
-  std::unordered_map<int64_t, std::array<int, 3>> pts;
+  std::vector<uint8_t> mark(nm.cov.size(), 0);  // cells to cover, over the map region
   int64_t f = 0;
   for (int gi : h->level_grids[level]) {
     const amr_grid& G = h->grids[gi];
@@ -2237,7 +2235,7 @@ std::vector<amr_grid> do_regrid(amr_hierarchy* h, int level, amr_state* Ul, amr_
               for (int dx = -b; dx <= b; ++dx) {
                 int x[3] = {G.lo[0] + i + dx, G.lo[1] + j + dy, G.lo[2] + k + dz};
                 if (!nm.nestable(x)) continue;  // also wraps x
-                pts.emplace(key(x), std::array<int, 3>{x[0], x[1], x[2]});
+                mark[nm.at(x)] = 1;
               }
         }
   }
@@ -2258,12 +2256,16 @@ std::vector<amr_grid> do_regrid(amr_hierarchy* h, int level, amr_state* Ul, amr_
             if (!nm.nestable(x))
               throw Error(AMR_EINVAL, "grid " + std::to_string(gi) + " of level " + std::to_string(level + 2) +
                                           " cannot nest in level " + std::to_string(level));
-            pts.emplace(key(x), std::array<int, 3>{x[0], x[1], x[2]});
+            mark[nm.at(x)] = 1;
           }
     }
   std::vector<std::array<int, 3>> pv;
-  pv.reserve(pts.size());
-  for (auto& kv : pts) pv.push_back(kv.second);
+  for (int k = 0; k < nm.ext[2]; ++k)
+    for (int j = 0; j < nm.ext[1]; ++j)
+      for (int i = 0; i < nm.ext[0]; ++i) {
+        const int x[3] = {nm.lo[0] + i, nm.lo[1] + j, nm.lo[2] + k};
+        if (mark[nm.at(x)]) pv.push_back(std::array<int, 3>{x[0], x[1], x[2]});
+      }
   const int Nl[3] = {nm.N[0], nm.N[1], nm.N[2]};
   std::vector<IBox> boxes =
       cluster_boxes(nd, Nl, pv, rp->efficiency, rp->max_box, [&](const IBox& B) { return nm.box(B); });
