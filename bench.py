@@ -284,7 +284,7 @@ def amr_workload(args, deep=False):
 
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
             "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
-            "tune": tune, "regrid": None if deep else regrid_measure}
+            "tune": tune, "regrid": None if deep else regrid_measure, "schedules": True}
 
 
 def single_workload(args):
@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-regrid", action="store_true", help="skip the regrid measurement (3-level workload)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "0", "1"],
+                    help="launch-cycle schedule: window start (0), predictive eta balance (1), or the faster")
     ap.add_argument("--regrid-theta", type=float, default=0.03,
                     help="flag threshold of the measured regrid (relative centred density jump)")
     ap.add_argument("--regrid-eff", type=float, default=0.5, help="clustering efficiency of the measured regrid")
@@ -431,6 +433,22 @@ def main():
         for _ in range(2):
             W["eager"]()
         torch.cuda.synchronize()
+    sched = None
+    if W.get("schedules"):
+        # launch-cycle schedule: window start (0) or the predictive eta
+        # balance (1); both compute the same bits, the faster one is timed
+        ncyc = 2 ** (H.nlevels - 1)
+        cand = [0, 1] if args.schedule == "auto" else [int(args.schedule)]
+        ms = {}
+        for sc in cand:
+            H.set_schedule(sc)
+            W["eager"]()
+            ms[sc] = timed(W["eager"], 3) / 3
+        best = min(ms, key=ms.get)
+        H.set_schedule(best)
+        _, work = A.amr_get_schedule(H.h, ncyc)
+        sched = {"chosen": best, "eager_ms": {str(k): round(v, 4) for k, v in ms.items()},
+                 "predicted_cycle_work": [round(x) for x in work]}
     if W["prepare"]:
         W["prepare"]()
         torch.cuda.synchronize()
@@ -495,6 +513,8 @@ def main():
         out["batched_over_per_grid"] = value / per_grid
     if tuned is not None:
         out["autotune"] = tuned
+    if sched is not None:
+        out["schedule"] = sched
     if W.get("regrid") and not args.no_regrid:
         out["regrid"] = W["regrid"]()
     if not args.no_adjoint:

@@ -344,6 +344,37 @@ amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first
  * forward-mode dual number.  `which` out of range or ntrials < 1 returns -1. */
 double amr_selfcheck_adjoint(int32_t which, int32_t ntrials, uint64_t seed);
 
+/* ---- predictive balancing of launch cycles ----
+ * One coarse step runs R^(L-1) launch cycles.  Step k of a level-l grid has
+ * a window of W = R^(L-1-l) cycles, [k W, (k+1) W): its band is filled at the
+ * window's start and its result is first needed (registers, synchronisation,
+ * its next step) at the window's end, so it may run in any cycle of the
+ * window.  Schedule 0 runs it at the window's start (the level order of
+ * Sec. 4).  Schedule 1 applies the paper's predictive load balancing (Sec. 5,
+ * eta_l^p = sum_{l' <= l} (s_l' g_l'^p - w_l'^p) and g_l^p = gbar_l -
+ * (eta_{l-1}^p - etabar_{l-1}) / s_l, which makes eta_l^p equal for all p)
+ * with launch cycles in place of processors: levels are placed finest first
+ * (the finest level steps in every cycle and cannot move); for each window
+ * of level l, with eta(c) the predicted work already in cycle c, the level's
+ * share of cycle c is gbar - (eta(c) - etabar); grids are dealt largest first
+ * to the cycle with the largest unfilled share (lowest cycle on ties).
+ * Predicted work of one step: the cells of the flux kernel's computed region,
+ * prod_d (n_d + 2 band - 2).  The schedule changes where each grid's step is
+ * launched, never the arithmetic: results are bitwise equal. */
+
+/* Host-only plan (no GPU, no device tables): cycle_work (host, R^(L-1)
+ * doubles, may be NULL) receives the predicted work per cycle; step_cycle
+ * (host, may be NULL) receives, for each grid in order, the cycle of each of
+ * its R^level steps, concatenated. */
+amr_status amr_plan_schedule(const amr_params* p, const amr_grid* grids, int32_t ngrids, int32_t schedule,
+                             double* cycle_work, int32_t* step_cycle);
+/* Schedule of amr_coarse_step() and of coarse steps captured afterwards
+ * (0 or 1; captured graphs of the other schedule are dropped). */
+amr_status amr_set_schedule(amr_hierarchy* h, int32_t schedule);
+/* Current schedule and, if cycle_work is not NULL, its predicted work per
+ * cycle (R^(L-1) doubles). */
+amr_status amr_get_schedule(const amr_hierarchy* h, int32_t* schedule, double* cycle_work);
+
 /* ---- regridding and the (O)verlap transfer ----
  * The mesh is adaptive: each level has successive iterations of grids, and
  * the fluid variables move from the previous iteration to the current one

@@ -102,6 +102,10 @@ def lib():
         L.amr_kernel_times.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.amr_cluster_boxes.argtypes = [C.c_int32, C.POINTER(C.c_int32), _VP, _VP, C.c_double, C.c_int32,
                                         C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        L.amr_plan_schedule.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.amr_set_schedule.argtypes = [_VP, C.c_int32]
+        L.amr_get_schedule.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.amr_level_cells.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int64)]
         L.amr_flag_cells.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), C.c_double, _VP,
                                      _VP]
@@ -340,6 +344,34 @@ def amr_cluster_boxes(mask, admissible=None, efficiency=0.7, max_box=16):
         return [(tuple(out[6 * q:6 * q + nd]), tuple(out[6 * q + 3:6 * q + 3 + nd])) for q in range(n.value)]
 
 
+def amr_plan_schedule(params, grids, schedule):
+    """Host-only plan: (predicted work per cycle, per grid the cycle of each
+    of its steps)."""
+    recs = make_grids(grids)
+    arr = (amr_grid * len(recs))(*recs)
+    ncyc = params.ratio ** (params.nlevels - 1)
+    work = (C.c_double * ncyc)()
+    nsteps = [params.ratio ** g.level for g in recs]
+    sc = (C.c_int32 * sum(nsteps))()
+    _check(lib().amr_plan_schedule(C.byref(params), arr, len(recs), schedule, work, sc), "amr_plan_schedule")
+    out, q = [], 0
+    for n in nsteps:
+        out.append(list(sc[q:q + n]))
+        q += n
+    return list(work), out
+
+
+def amr_set_schedule(h, schedule):
+    _check(lib().amr_set_schedule(h, schedule), "amr_set_schedule")
+
+
+def amr_get_schedule(h, ncycles):
+    s = C.c_int32()
+    work = (C.c_double * ncycles)()
+    _check(lib().amr_get_schedule(h, C.byref(s), work), "amr_get_schedule")
+    return s.value, list(work)
+
+
 def amr_level_cells(h, level):
     n = C.c_int64()
     _check(lib().amr_level_cells(h, level, C.byref(n)), "amr_level_cells")
@@ -478,6 +510,9 @@ class Hierarchy:
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua
+
+    def set_schedule(self, schedule):
+        amr_set_schedule(self.h, schedule)
 
     def flags(self, level, U, Up, theta):
         """Refinement flags of `level` (uint8 tensor in the flag layout)."""

@@ -111,6 +111,11 @@ struct amr_hierarchy {
 
   // launch lists
   std::vector<LaunchList> cycle_lists;                 // per launch cycle (batched)
+  // eta-balanced schedule: the grids of a level step anywhere inside the
+  // cycles of their step's window (see plan_eta); predicted work per cycle
+  int schedule = 0;  // 0: every level at the start of its window; 1: eta-balanced
+  std::vector<LaunchList> eta_lists;
+  std::vector<double> cycle_work[2];
   std::map<std::pair<int, int>, LaunchList> grid_lists;  // (grid, band) -> per-grid list
   std::map<int, LaunchList> level0_band_lists;          // band -> all level-0 grids
   std::vector<LaunchList> band2_lists;                  // per level: all its grids, band 2
@@ -369,6 +374,68 @@ int64_t cells_of(const amr_grid& G) {
   return (int64_t)(G.hi[0] - G.lo[0]) * (G.hi[1] - G.lo[1]) * (G.hi[2] - G.lo[2]);
 }
 
+// Predicted cost of one step of grid gi from band gv: the cells of the
+// flux kernel's computed region.
+double step_work(const amr_hierarchy* h, int gi, int gv) {
+  double w = 1.0;
+  for (int a = 0; a < h->ndim; ++a) w *= (double)(h->grids[gi].hi[a] - h->grids[gi].lo[a] + 2 * gv - 2);
+  return w;
+}
+
+// Cycle of every step of every grid in one coarse step: cyc[gi][k] for the
+// k-th step of grid gi (k < R^level).  The step k of a level-l grid may run
+// in any launch cycle of its window [k W, (k+1) W), W = R^(L-1-l): its band
+// is filled at the window's start and its result is first needed (registers,
+// synchronisation, the next step) at the window's end.  Schedule 0 runs it
+// at the window's start.  Schedule 1 spreads each window's grids over the
+// window's cycles with the paper's predictive balancing (Sec. 5), launch
+// cycles standing in for processors: with eta(c) the work already placed in
+// cycle c by the finer levels (placed first: the finest level cannot move),
+// the level's share of cycle c is g(c) = gbar - (eta(c) - etabar) (gbar its
+// mean work per cycle of the window, etabar the window's mean eta), which
+// makes eta(c) + g(c) equal over the window; grids are dealt largest first
+// to the cycle with the largest unfilled share (lowest cycle on ties).
+void plan_eta(const amr_hierarchy* h, int schedule, std::vector<std::vector<int>>& cyc, std::vector<double>& load) {
+  const int L = h->nlev, R = h->R;
+  const int ncyc = ipow(R, L - 1);
+  cyc.assign(h->grids.size(), {});
+  load.assign(ncyc, 0.0);
+  for (int l = L - 1; l >= 0; --l) {
+    const int span = ipow(R, L - 1 - l), nsteps = ipow(R, l);
+    for (int gi : h->level_grids[l]) cyc[gi].assign(nsteps, 0);
+    for (int k = 0; k < nsteps; ++k) {
+      const int c0 = k * span;
+      const int gv = l == 0 ? h->g : h->g - 2 * (k % R);
+      std::vector<std::pair<double, int>> w;
+      double tot = 0.0;
+      for (int gi : h->level_grids[l]) {
+        w.push_back({step_work(h, gi, gv), gi});
+        tot += w.back().first;
+      }
+      std::vector<double> share(span, 0.0), got(span, 0.0);
+      if (schedule == 1 && span > 1) {
+        double etabar = 0.0;
+        for (int c = 0; c < span; ++c) etabar += load[c0 + c];
+        etabar /= span;
+        const double gbar = tot / span;
+        for (int c = 0; c < span; ++c) share[c] = gbar - (load[c0 + c] - etabar);
+        std::stable_sort(w.begin(), w.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+          return a.first > b.first || (a.first == b.first && a.second < b.second);
+        });
+      }
+      for (auto& wg : w) {
+        int best = 0;
+        if (schedule == 1)
+          for (int c = 1; c < span; ++c)
+            if (share[c] - got[c] > share[best] - got[best]) best = c;
+        got[best] += wg.first;
+        cyc[wg.second][k] = c0 + best;
+      }
+      for (int c = 0; c < span; ++c) load[c0 + c] += got[c];
+    }
+  }
+}
+
 void build_lists(amr_hierarchy* h) {
   const int L = h->nlev;
   const int ncyc = ipow(h->R, L - 1);
@@ -387,6 +454,29 @@ void build_lists(amr_hierarchy* h) {
       for (int gi : gl) gb.push_back({gi, gv});
     }
     h->cycle_lists.push_back(make_list(h, gb));
+  }
+  // eta-balanced lists: same items, each (grid, step) in the cycle plan_eta
+  // gives it; finest level first, larger grids first within a level
+  {
+    std::vector<std::vector<int>> cyc;
+    plan_eta(h, 1, cyc, h->cycle_work[1]);
+    std::vector<std::vector<int>> cyc0;
+    plan_eta(h, 0, cyc0, h->cycle_work[0]);
+    for (int c = 0; c < ncyc; ++c) {
+      std::vector<std::pair<int, int>> gb;
+      for (int l = L - 1; l >= 0; --l) {
+        const int span = ipow(h->R, L - 1 - l);
+        const int k = c / span;
+        const int gv = l == 0 ? h->g : h->g - 2 * (k % h->R);
+        std::vector<int> gl;
+        for (int gi : h->level_grids[l])
+          if (cyc[gi][k] == c) gl.push_back(gi);
+        std::stable_sort(gl.begin(), gl.end(),
+                         [&](int a, int b) { return cells_of(h->grids[a]) > cells_of(h->grids[b]); });
+        for (int gi : gl) gb.push_back({gi, gv});
+      }
+      h->eta_lists.push_back(make_list(h, gb));
+    }
   }
   // per-grid lists for every band the per-grid path may use
   for (int gi = 0; gi < (int)h->grids.size(); ++gi)
@@ -1126,19 +1216,26 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
   do_fill<T>(h, 0, AMR_FILL_SAME_LEVEL, cur(0), cur(0), s);
   if (mode == 0) {
     const int ncyc = ipow(R, L - 1);
+    const std::vector<LaunchList>& lists = h->schedule == 1 ? h->eta_lists : h->cycle_lists;
     for (int c = 0; c < ncyc; ++c) {
-      uint32_t stepping = 0;
-      for (int l = 0; l < L; ++l) {
+      // band fills of the levels whose step window starts here
+      for (int l = 1; l < L; ++l) {
         const int span = ipow(R, L - 1 - l);
         if (c % span) continue;
-        stepping |= 1u << l;
         const int k = c / span;
-        if (l > 0) do_fill<T>(h, l, (k % R == 0) ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s);
+        do_fill<T>(h, l, (k % R == 0) ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s);
       }
-      run_list<T>(h, h->cycle_lists[c], Ua, Ub, par, dt0, ws, s);
-      for (int l = 0; l < L; ++l)
-        if (stepping >> l & 1u) write_registers<T>(h, l, c / ipow(R, L - 1 - l), dt0, ws, s);
-      par ^= stepping;
+      run_list<T>(h, lists[c], Ua, Ub, par, dt0, ws, s);
+      // levels whose window ends here: every grid has stepped; registers,
+      // then the level's buffers swap, then the synchronisations it closes
+      uint32_t ending = 0;
+      for (int l = 0; l < L; ++l) {
+        const int span = ipow(R, L - 1 - l);
+        if ((c + 1) % span) continue;
+        ending |= 1u << l;
+        write_registers<T>(h, l, c / span, dt0, ws, s);
+      }
+      par ^= ending;
       for (int f = L - 1; f >= 1; --f)
         if ((c + 1) % ipow(R, L - f) == 0) do_sync<T>(h, f, cur(f), cur(f - 1), ws, s);
     }
@@ -1302,6 +1399,60 @@ amr_status amr_validate(const amr_params* p, const amr_grid* grids, int32_t ngri
     delete h;
     return fail(e);
   }
+}
+
+amr_status amr_plan_schedule(const amr_params* p, const amr_grid* grids, int32_t ngrids, int32_t schedule,
+                             double* cycle_work, int32_t* step_cycle) {
+  try {
+    if (schedule != 0 && schedule != 1) throw Error(AMR_EINVAL, "schedule must be 0 or 1");
+    validate(p, grids, ngrids);
+    amr_hierarchy h;
+    h.p = *p;
+    h.ndim = p->ndim;
+    h.nlev = p->nlevels;
+    h.R = p->ratio;
+    h.g = p->ghost;
+    h.grids.assign(grids, grids + ngrids);
+    h.level_grids.assign(h.nlev, {});
+    for (int i = 0; i < ngrids; ++i) h.level_grids[grids[i].level].push_back(i);
+    std::vector<std::vector<int>> cyc;
+    std::vector<double> load;
+    plan_eta(&h, schedule, cyc, load);
+    if (cycle_work) std::copy(load.begin(), load.end(), cycle_work);
+    if (step_cycle) {
+      size_t q = 0;
+      for (int i = 0; i < ngrids; ++i)
+        for (int c : cyc[i]) step_cycle[q++] = c;
+    }
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_set_schedule(amr_hierarchy* h, int32_t schedule) {
+  try {
+    if (!h) throw Error(AMR_EINVAL, "null argument");
+    if (schedule != 0 && schedule != 1) throw Error(AMR_EINVAL, "schedule must be 0 or 1");
+    if (schedule != h->schedule) {
+      for (auto& g : h->graph_exec)
+        if (g) {
+          (void)hipGraphExecDestroy(g);
+          g = nullptr;
+        }
+      h->schedule = schedule;
+    }
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_get_schedule(const amr_hierarchy* h, int32_t* schedule, double* cycle_work) {
+  if (!h || !schedule) return AMR_EINVAL;
+  *schedule = h->schedule;
+  if (cycle_work) std::copy(h->cycle_work[h->schedule].begin(), h->cycle_work[h->schedule].end(), cycle_work);
+  return AMR_OK;
 }
 
 amr_status amr_destroy(amr_hierarchy* h) {
@@ -1555,6 +1706,7 @@ void rebuild_lists(amr_hierarchy* h) {
   h->h_fitems.clear();
   h->h_uitems.clear();
   h->cycle_lists.clear();
+  h->eta_lists.clear();
   h->grid_lists.clear();
   h->level0_band_lists.clear();
   h->band2_lists.clear();

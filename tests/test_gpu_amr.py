@@ -186,3 +186,40 @@ def test_autotune_keeps_the_state_and_the_results():
     for gg, gw in zip(got, ref):
         for x, y in zip(gg, gw):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("key", ["3d", "2d"])
+def test_eta_schedule_gives_identical_results(key):
+    """The predictive (eta) schedule moves coarse-level grid steps to other
+    launch cycles of their window; two coarse steps agree bit for bit with
+    the window-start schedule, eager and as graph replays."""
+    import torch
+    ndim, N0, L, grids, fields = _setup(key)
+    ref, dref, _ = amr_gpu(ndim, N0, L, grids, fields, 2)
+    H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
+    H.set_schedule(1)
+    ncyc = 2 ** (L - 1)
+    sched, work = A.amr_get_schedule(H.h, ncyc)
+    log(f"case: eta schedule {key}, predicted work per cycle {[round(w) for w in work]}")
+    assert sched == 1
+    for graph in (False, True):
+        Ua, Ub = H.new_state(), H.new_state()
+        for gi, f in enumerate(fields):
+            H.load_primitive(Ua, gi, f["prim"], f["b"])
+        par = 0
+        stream = torch.cuda.Stream()
+        if graph:
+            with torch.cuda.stream(stream):
+                H.graph_capture(Ua, Ub, 0)
+            torch.cuda.synchronize()
+            for gi, f in enumerate(fields):
+                H.load_primitive(Ua, gi, f["prim"], f["b"])
+        for _ in range(2):
+            with torch.cuda.stream(stream):
+                par = H.graph_launch(par) if graph else H.coarse_step(Ua, Ub, par, 0)
+            torch.cuda.synchronize()
+        got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
+        assert H.error_flags()[0] == 0
+        for gg, gw in zip(got, ref):
+            for x, y in zip(gg, gw):
+                assert np.array_equal(x, y), f"graph={graph}"

@@ -47,6 +47,30 @@ def test_deep_subvolume_f64_matches_oracle(case):
     assert np.all(err <= 1e-10), err
 
 
+def test_deep_subvolume_eta_schedule_bitwise(case):
+    """Six levels: under the predictive (eta) schedule, grid steps move
+    across windows of up to 32 launch cycles; one coarse step agrees bit for
+    bit with the window-start schedule."""
+    import torch
+    grids, fields, want, dts = case
+    outs = []
+    for sched in (0, 1):
+        H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4, dtype="f64")
+        H.set_schedule(sched)
+        Ua, Ub = H.new_state(), H.new_state()
+        for gi, f in enumerate(fields):
+            H.load_primitive(Ua, gi, f["prim"], f["b"])
+        par = H.coarse_step(Ua, Ub, 0, 0)
+        torch.cuda.synchronize()
+        assert H.error_flags()[0] == 0
+        outs.append([H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)])
+        _, work = A.amr_get_schedule(H.h, 2 ** (L - 1))
+        log(f"  schedule {sched}: predicted work per cycle min {min(work):.3g} max {max(work):.3g}")
+    for ga, gb in zip(*outs):
+        for x, y in zip(ga, gb):
+            assert np.array_equal(x, y)
+
+
 def test_deep_subvolume_f32_autotuned_graph_matches_oracle(case):
     """FP32, autotuned launch configuration, coarse step replayed from a
     captured HIP graph."""
