@@ -213,7 +213,7 @@ State<T> run(State<T> S, int nsteps, const double* dts, const StepParams& P) {
 }
 
 StepParams params(int ndim, const int* n, double gamma) {
-  return StepParams{gamma, {1.0 / n[0], 1.0 / n[1], ndim == 3 ? 1.0 / n[2] : 1.0}};
+  return StepParams{gamma, {1.0 / n[0], 1.0 / n[1], ndim == 3 ? 1.0 / n[2] : 1.0}, 0};
 }
 
 double cell_volume(int ndim, const int* n) {

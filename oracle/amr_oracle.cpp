@@ -307,7 +307,7 @@ struct Amr {
     if (dry) return;
     const int gv = l == 0 ? g : g - 2 * (k % R);
     const double dt = dt0 / ipow(R, l);
-    StepParams P{gamma, {dx(l, 0), dx(l, 1), dx(l, 2)}};
+    StepParams P{gamma, {dx(l, 0), dx(l, 1), dx(l, 2)}, emf_mode()};
     per_grid(l, [&](int gi) {
       Grid& q = G[gi];
       State<double> out(q.S.L);

@@ -41,6 +41,32 @@ def lib():
     return _LIB
 
 
+def set_emf(mode):
+    """Edge EMF of the oracle's later steps: 0 arithmetic mean (Balsara &
+    Spicer 1999), 1 upwinded (Gardiner & Stone 2005); 2 is 1 with the upwind
+    side swapped (a planted mistake for sensitivity tests).  Returns the
+    previous."""
+    old = lib().orc_set_emf(int(mode))
+    if old < 0:
+        raise ValueError("emf mode must be 0, 1 or 2")
+    return old
+
+
+class emf:
+    """Context manager: `with emf(1): ...` runs the oracle with upwinded EMFs."""
+
+    def __init__(self, mode):
+        self.mode = mode
+
+    def __enter__(self):
+        self.old = set_emf(self.mode)
+        return self
+
+    def __exit__(self, *exc):
+        set_emf(self.old)
+        return False
+
+
 def _err():
     return lib().orc_last_error().decode()
 

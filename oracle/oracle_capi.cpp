@@ -145,6 +145,17 @@ void store_interior(const State<double>& S, double* const* out) {
 
 extern "C" {
 
+// Edge EMF of every later step: 0 arithmetic mean (Balsara & Spicer), 1
+// upwinded (Gardiner & Stone); 2 is 1 with the upwind side swapped, a
+// planted mistake that only the sensitivity tests use.  Returns the previous
+// choice, or -1 for a bad value (unchanged).
+int orc_set_emf(int mode) {
+  if (mode < 0 || mode > 2) return -1;
+  const int old = emf_mode();
+  emf_mode() = mode;
+  return old;
+}
+
 const char* orc_last_error() { return g_err.c_str(); }
 
 int orc_max_threads() {
@@ -196,7 +207,7 @@ int orc_uniform_run(int ndim, const int* n, const int* bc, double gamma, double 
   try {
     if (fill_every < 1 || 2 * fill_every > g) return fail("need 1 <= fill_every and 2*fill_every <= g");
     Layout L = make_layout(ndim, n, g);
-    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}};
+    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}, emf_mode()};
     State<double> S = load_primitive(L, prim, bface, bc, gamma);
     State<double> T2(L);
     int gv = g;
@@ -224,7 +235,7 @@ double orc_uniform_time(int ndim, const int* n, const int* bc, double gamma, dou
                         int fill_every, int nsteps, const double* const* prim, const double* const* bface) {
   try {
     Layout L = make_layout(ndim, n, g);
-    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}};
+    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}, emf_mode()};
     State<double> S = load_primitive(L, prim, bface, bc, gamma);
     State<double> T2(L);
     int gv = g;
@@ -254,7 +265,7 @@ int orc_step_banded(int ndim, const int* n, int g, int gv, double gamma, const d
                     const double* const* in, double* const* out) {
   try {
     Layout L = make_layout(ndim, n, g);
-    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}};
+    StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}, emf_mode()};
     State<double> S(L), O(L);
     for (int s = 0; s < NVAR; ++s) std::memcpy(S.f[s].data(), in[s], L.fsize(s) * sizeof(double));
     step(S, O, gv, dt, P);
@@ -283,7 +294,7 @@ int orc_fill_banded(int ndim, const int* n, int g, const int* bc, double* const*
 double orc_dt_banded(int ndim, const int* n, int g, double gamma, double cfl, const double* dx,
                      const double* const* f) {
   Layout L = make_layout(ndim, n, g);
-  StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}};
+  StepParams P{gamma, {dx[0], dx[1], ndim > 2 ? dx[2] : 1.0}, emf_mode()};
   State<double> S(L);
   for (int s = 0; s < NVAR; ++s) std::memcpy(S.f[s].data(), f[s], L.fsize(s) * sizeof(double));
   return cfl_dt(S, P, cfl);
