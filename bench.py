@@ -100,7 +100,8 @@ def single_grid_workload(args):
     dtype = args.dtype
     n = (N, N, N)
     ic = I.smooth_mhd(3, n, seed=2, v_rms=0.1, b_rms=0.3, jump=True)
-    H = A.Hierarchy(3, n, [(0, (0, 0, 0), n)], ghost=4, dtype=dtype, dx0=ic["dx"], gamma=GAMMA, cfl=0.4)
+    H = A.Hierarchy(3, n, [(0, (0, 0, 0), n)], ghost=4, dtype=dtype, dx0=ic["dx"], gamma=GAMMA, cfl=0.4,
+                    emf=EMF[args.emf])
     U, V = H.new_state(), H.new_state()
     H.load_primitive(U, 0, ic["prim"], ic["b"])
     state = {"U": U, "V": V, "s": 0}
@@ -162,7 +163,7 @@ def amr_workload(args, deep=False):
         L = 3
         grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
         fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
-    H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4, dtype=args.dtype)
+    H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4, dtype=args.dtype, emf=EMF[args.emf])
     Ua, Ub = H.new_state(), H.new_state()
     for gi, f in enumerate(fields):
         H.load_primitive(Ua, gi, f["prim"], f["b"])
@@ -293,6 +294,8 @@ def single_workload(args):
             "flux_flops": flops, "info": info, "cpu_sample": cpu, "tune": tune}
 
 
+EMF = {"mean": 0, "upwind": 1}
+
 WORKLOADS = {"amr3": amr_workload, "single128": single_workload, "deep6": lambda a: amr_workload(a, deep=True)}
 
 
@@ -358,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--emf", default="mean", choices=sorted(EMF),
+                    help="edge EMF of constrained transport: arithmetic mean or upwinded (Gardiner-Stone)")
     ap.add_argument("--no-regrid", action="store_true", help="skip the regrid measurement (3-level workload)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "0", "1"],
                     help="launch-cycle schedule: window start (0), predictive eta balance (1), or the faster")
@@ -497,7 +502,8 @@ def main():
         "vs_baseline": None,
         "dtype": info["dtype"],
         "data": "synthetic",
-        "config": {"workload": info["workload"], "grids": info["grids"],
+        "config": {"workload": info["workload"] + ("; upwinded (Gardiner-Stone) CT EMF" if args.emf == "upwind" else ""),
+                   "grids": info["grids"],
                    "useful_cell_updates_per_step": info["cells"], "parallelism": "single GPU"},
         "roofline": {"kernel": "k_flux", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,

@@ -70,7 +70,20 @@ typedef struct {
 /* Problem parameters.  ghost = g, the band width in cells of the grid's own
  * level; g >= 2 on a single level and g >= 2R when nlevels > 1 so that a fine
  * grid runs its R substeps from one fill (each step consumes 2 band cells).
- * domain = level-0 cells per axis; dx0 = level-0 cell widths; R = ratio. */
+ * domain = level-0 cells per axis; dx0 = level-0 cell widths; R = ratio.
+ * emf = edge EMF of the constrained-transport update:
+ *   AMR_EMF_MEAN (0): the arithmetic mean of the four adjacent face values
+ *     (Balsara & Spicer 1999, J. Comput. Phys. 149, 270);
+ *   AMR_EMF_UPWIND (1): the upwinded EMF of Gardiner & Stone (2005,
+ *     J. Comput. Phys. 205, 509): that mean plus half-cell differences between
+ *     face values and a cell-centred reference EMF, each on the upwind side
+ *     of the mass flux through its face.  The reference is -v x B with v of
+ *     the Hancock half-step cell state and B the cell-centred field at time n
+ *     (the time of the normal field the Riemann problems use), so for flow
+ *     along a grid axis the edge EMF is exactly the face flux of that axis.
+ *     Three more arrays in the workspace; the adjoint and the frozen-branch
+ *     forward support AMR_EMF_MEAN only (AMR_EUNSUPPORTED). */
+typedef enum { AMR_EMF_MEAN = 0, AMR_EMF_UPWIND = 1 } amr_emf;
 typedef struct {
   int32_t ndim;      /* 2 or 3 */
   int32_t nlevels;   /* >= 1 */
@@ -82,6 +95,8 @@ typedef struct {
   double dx0[3];
   double gamma;      /* ratio of specific heats */
   double cfl;        /* Courant number C of the time step */
+  int32_t emf;       /* amr_emf */
+  int32_t pad;
 } amr_params;
 
 /* Eight device pools (see Memory above). */

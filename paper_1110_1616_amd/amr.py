@@ -22,6 +22,7 @@ AMR_OK, AMR_EINVAL, AMR_EHIP, AMR_ENOMEM, AMR_ESTATE, AMR_EUNSUPPORTED = 0, -1, 
 AMR_F32, AMR_F64 = 0, 1
 AMR_BC_PERIODIC, AMR_BC_OUTFLOW = 0, 1
 AMR_FILL_FULL, AMR_FILL_SAME_LEVEL = 0, 1
+AMR_EMF_MEAN, AMR_EMF_UPWIND = 0, 1
 FIELDS = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
 
 
@@ -32,7 +33,7 @@ class amr_grid(C.Structure):
 class amr_params(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("nlevels", C.c_int32), ("ratio", C.c_int32), ("ghost", C.c_int32),
                 ("dtype", C.c_int32), ("bc", C.c_int32 * 3), ("domain", C.c_int32 * 3), ("dx0", C.c_double * 3),
-                ("gamma", C.c_double), ("cfl", C.c_double)]
+                ("gamma", C.c_double), ("cfl", C.c_double), ("emf", C.c_int32), ("pad", C.c_int32)]
 
 
 class amr_state(C.Structure):
@@ -158,7 +159,7 @@ def amr_validate(params, grids):
 
 
 def make_params(ndim, domain, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0, 0), dx0=None, gamma=5.0 / 3.0,
-                cfl=0.4):
+                cfl=0.4, emf=AMR_EMF_MEAN):
     domain = tuple(domain) + (1,) * (3 - len(domain))
     p = amr_params()
     p.ndim, p.nlevels, p.ratio, p.ghost = ndim, nlevels, ratio, ghost
@@ -168,6 +169,7 @@ def make_params(ndim, domain, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0
         p.domain[d] = domain[d]
         p.dx0[d] = (dx0[d] if dx0 is not None else 1.0 / domain[d]) if d < ndim else 1.0
     p.gamma, p.cfl = gamma, cfl
+    p.emf = emf
     return p
 
 
@@ -425,7 +427,7 @@ class Hierarchy:
     """A grid hierarchy handle plus the torch-owned memory sized for it."""
 
     def __init__(self, ndim, domain, grids, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0, 0), dx0=None,
-                 gamma=5.0 / 3.0, cfl=0.4, device="cuda"):
+                 gamma=5.0 / 3.0, cfl=0.4, device="cuda", emf=AMR_EMF_MEAN):
         import torch
         self.torch = torch
         self.ndim = ndim
@@ -435,7 +437,7 @@ class Hierarchy:
         self.ghost = ghost
         self.gamma = gamma
         self.dtype = torch.float64 if dtype == "f64" else torch.float32
-        p = make_params(ndim, domain, nlevels, ratio, ghost, dtype, bc, dx0, gamma, cfl)
+        p = make_params(ndim, domain, nlevels, ratio, ghost, dtype, bc, dx0, gamma, cfl, emf)
         self.params = p
         self.grid_records = make_grids(grids)
         self.grids = [(g.level, tuple(g.lo), tuple(g.hi)) for g in self.grid_records]

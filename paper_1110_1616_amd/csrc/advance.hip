@@ -11,6 +11,7 @@
 // read each tile's grid descriptor, so one launch covers every grid that
 // steps in a launch cycle.
 #include <algorithm>
+#include <type_traits>
 
 #include "advance_common.hpp"
 #include "amr_internal.hpp"
@@ -101,7 +102,7 @@ __device__ __forceinline__ void retire(WorkQueue* q) {
   }
 }
 
-template <class T, int NDIM, bool PERSIST>
+template <class T, int NDIM, bool PERSIST, bool UPWIND>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                               DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err,
@@ -197,7 +198,27 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
         }
         if ((wcur[0] <= T(0)) || (wcur[4] <= T(0))) flag_bad(err, ix(cx, cy, k));
         const int64_t e = ix(cx, cy, k);
-        bool ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fbcur, hdt, idx, gam, pr);
+        bool ok;
+        if constexpr (UPWIND) {
+          T du[8];
+          ok = predict_du<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fbcur, hdt, idx, gam, pr, du);
+          // reference EMF of the upwinded CT: -v x B with v of the half-step
+          // cell state U + du and B at time n; one writer per cell (the
+          // tile's own cells, plus the grid's first column / row / plane)
+          if (k >= item.z0 && (tx >= 1 || cx == cl) && (ty >= 1 || cy == cl)) {
+            const T ir = T(1) / (wcur[0] + du[0]);
+            const T vx = (wcur[0] * wcur[1] + du[1]) * ir;
+            const T vy = (wcur[0] * wcur[2] + du[2]) * ir;
+            const T vz = (wcur[0] * wcur[3] + du[3]) * ir;
+            if (NDIM == 3) {
+              F.e[0][e] = vz * wcur[6] - vy * wcur[7];
+              F.e[1][e] = vx * wcur[7] - vz * wcur[5];
+            }
+            F.e[2][e] = vy * wcur[5] - vx * wcur[6];
+          }
+        } else {
+          ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fbcur, hdt, idx, gam, pr);
+        }
         if (!ok) flag_bad(err, e);
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
@@ -256,7 +277,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
   retire<PERSIST>(q);
 }
 
-template <class T, int NDIM, bool PERSIST>
+template <class T, int NDIM, bool PERSIST, bool UPWIND>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
                                                 int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                                 DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, WorkQueue* q,
@@ -320,23 +341,23 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
       if (NDIM == 3) {
         // faces: dB_d/dt = -(curl E)_d
         if (cy < uhy && k < uhz) {  // Bx face (cx, cy, k)
-          T ez0 = edge_emf<2>(F, e, st), ez1 = edge_emf<2>(F, e + st[1], st);
-          T ey0 = edge_emf<1>(F, e, st), ey1 = edge_emf<1>(F, e + st[2], st);
+          T ez0 = emf_at<2, UPWIND>(F, e, st), ez1 = emf_at<2, UPWIND>(F, e + st[1], st);
+          T ey0 = emf_at<1, UPWIND>(F, e, st), ey1 = emf_at<1, UPWIND>(F, e + st[2], st);
           Uout.f[5][e] = Uin.f[5][e] - (cdy * (ez1 - ez0) - cdz * (ey1 - ey0));
         }
         if (cx < uhx && k < uhz) {  // By face
-          T ex0 = edge_emf<0>(F, e, st), ex1 = edge_emf<0>(F, e + st[2], st);
-          T ez0 = edge_emf<2>(F, e, st), ez1 = edge_emf<2>(F, e + st[0], st);
+          T ex0 = emf_at<0, UPWIND>(F, e, st), ex1 = emf_at<0, UPWIND>(F, e + st[2], st);
+          T ez0 = emf_at<2, UPWIND>(F, e, st), ez1 = emf_at<2, UPWIND>(F, e + st[0], st);
           Uout.f[6][e] = Uin.f[6][e] - (cdz * (ex1 - ex0) - cdx * (ez1 - ez0));
         }
         if (cx < uhx && cy < uhy) {  // Bz face
-          T ey0 = edge_emf<1>(F, e, st), ey1 = edge_emf<1>(F, e + st[0], st);
-          T ex0 = edge_emf<0>(F, e, st), ex1 = edge_emf<0>(F, e + st[1], st);
+          T ey0 = emf_at<1, UPWIND>(F, e, st), ey1 = emf_at<1, UPWIND>(F, e + st[0], st);
+          T ex0 = emf_at<0, UPWIND>(F, e, st), ex1 = emf_at<0, UPWIND>(F, e + st[1], st);
           Uout.f[7][e] = Uin.f[7][e] - (cdx * (ey1 - ey0) - cdy * (ex1 - ex0));
         }
       } else {
         // 2D: only E_z; edges are cell corners.
-        auto ez = [&](int64_t ee) { return edge_emf<2>(F, ee, st); };
+        auto ez = [&](int64_t ee) { return emf_at<2, UPWIND>(F, ee, st); };
         if (cy < uhy) {  // Bx face
           T e0 = ez(e), e1 = ez(e + st[1]);
           Uout.f[5][e] = Uin.f[5][e] - cdy * (e1 - e0);
@@ -356,41 +377,65 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 bool xcd, hipStream_t s) {
+                 bool xcd, bool upwind_emf, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
   const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
-  if (ndim == 3) {
-    if (per)
-      hipLaunchKernelGGL((k_flux<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
-    else
-      hipLaunchKernelGGL((k_flux<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
-  } else {
-    if (per)
-      hipLaunchKernelGGL((k_flux<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
-    else
-      hipLaunchKernelGGL((k_flux<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, q, xcd);
+#define AMR_FLUX_LAUNCH(ND, P, U)                                                                                  \
+  hipLaunchKernelGGL((k_flux<T, ND, P, U>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, \
+                     q, xcd)
+  if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+    if (upwind_emf) {
+      if (ndim == 3) {
+        if (per) AMR_FLUX_LAUNCH(3, true, true);
+        else AMR_FLUX_LAUNCH(3, false, true);
+      } else {
+        if (per) AMR_FLUX_LAUNCH(2, true, true);
+        else AMR_FLUX_LAUNCH(2, false, true);
+      }
+      return;
+    }
   }
+  if (ndim == 3) {
+    if (per) AMR_FLUX_LAUNCH(3, true, false);
+    else AMR_FLUX_LAUNCH(3, false, false);
+  } else {
+    if (per) AMR_FLUX_LAUNCH(2, true, false);
+    else AMR_FLUX_LAUNCH(2, false, false);
+  }
+#undef AMR_FLUX_LAUNCH
 }
 
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   bool xcd, hipStream_t s) {
+                   bool xcd, bool upwind_emf, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
   const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
-  if (ndim == 3) {
-    if (per)
-      hipLaunchKernelGGL((k_update<T, 3, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
-    else
-      hipLaunchKernelGGL((k_update<T, 3, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
-  } else {
-    if (per)
-      hipLaunchKernelGGL((k_update<T, 2, true>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
-    else
-      hipLaunchKernelGGL((k_update<T, 2, false>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, xcd);
+#define AMR_UPD_LAUNCH(ND, P, U)                                                                                   \
+  hipLaunchKernelGGL((k_update<T, ND, P, U>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, \
+                     xcd)
+  if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+    if (upwind_emf) {
+      if (ndim == 3) {
+        if (per) AMR_UPD_LAUNCH(3, true, true);
+        else AMR_UPD_LAUNCH(3, false, true);
+      } else {
+        if (per) AMR_UPD_LAUNCH(2, true, true);
+        else AMR_UPD_LAUNCH(2, false, true);
+      }
+      return;
+    }
   }
+  if (ndim == 3) {
+    if (per) AMR_UPD_LAUNCH(3, true, false);
+    else AMR_UPD_LAUNCH(3, false, false);
+  } else {
+    if (per) AMR_UPD_LAUNCH(2, true, false);
+    else AMR_UPD_LAUNCH(2, false, false);
+  }
+#undef AMR_UPD_LAUNCH
 }
 
 // Resident 256-thread blocks per CU of each kernel (for persistent launches).
@@ -398,11 +443,11 @@ template <class T>
 void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu) {
   int a = 0, b = 0;
   if (ndim == 3) {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 3, true>, 256, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 3, true>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 3, true, false>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 3, true, false>, 256, 0);
   } else {
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 2, true>, 256, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 2, true>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_flux<T, 2, true, false>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_update<T, 2, true, false>, 256, 0);
   }
   *flux_blocks_per_cu = a > 0 ? a : 1;
   *update_blocks_per_cu = b > 0 ? b : 1;
@@ -410,9 +455,9 @@ void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_
 
 #define AMR_ADV_INST(T)                                                                                             \
   template void launch_flux<T>(int, const GridDesc*, const FluxItem*, int, DevState<T>, DevState<T>, uint32_t,     \
-                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, hipStream_t);    \
+                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, bool, hipStream_t); \
   template void launch_update<T>(int, const GridDesc*, const UpdItem*, int, DevState<T>, DevState<T>, uint32_t,   \
-                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, bool, hipStream_t);
+                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, bool, bool, hipStream_t);
 AMR_ADV_INST(float)
 AMR_ADV_INST(double)
 // frozen-branch instances (finite-difference verification of the adjoint)

@@ -98,11 +98,13 @@ struct Pred {
 // emit(d, side, q) as soon as it is formed (side 0 low, 1 high), so callers
 // that store it right away never hold all 2*NDIM states in registers.
 // Returns false if a predicted density or pressure is not positive.
-template <class T, int NDIM, class Emit>
+// When WANT_DU, du_out receives the Hancock increment of the cell's
+// conserved state.
+template <class T, int NDIM, bool WANT_DU = false, class Emit>
 __device__ __forceinline__ bool predict_emit(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8],
                                              const T (&wym)[8], const T (&wyp)[8], const T (&wzm)[8],
                                              const T (&wzp)[8], const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
-                                             Emit&& emit) {
+                                             Emit&& emit, T (&du_out)[8]) {
   const T gm1 = gam - T(1);
   const T gm1_inv = T(1) / gm1;
   T sl[3][8];
@@ -139,6 +141,10 @@ __device__ __forceinline__ bool predict_emit(const T (&w)[8], const T (&wxm)[8],
 #pragma unroll
     for (int q = 0; q < 8; ++q) du[q] -= c * (fr[q] - fl[q]);
   }
+  if constexpr (WANT_DU) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) du_out[q] = du[q];
+  }
   bool ok = true;
 #pragma unroll
   for (int d = 0; d < NDIM; ++d) {
@@ -169,11 +175,25 @@ __device__ __forceinline__ bool predict(const T (&w)[8], const T (&wxm)[8], cons
                                         const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
                                         const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
                                         Pred<T, NDIM>& out) {
+  T unused[8];
   return predict_emit<T, NDIM>(w, wxm, wxp, wym, wyp, wzm, wzp, fb, hdt, idx, gam,
                                [&](int d, int side, const T (&q)[7]) {
 #pragma unroll
                                  for (int c = 0; c < 7; ++c) (side ? out.p[d] : out.m[d])[c] = q[c];
-                               });
+                               }, unused);
+}
+
+// predict() that also returns the Hancock increment du of the cell.
+template <class T, int NDIM>
+__device__ __forceinline__ bool predict_du(const T (&w)[8], const T (&wxm)[8], const T (&wxp)[8], const T (&wym)[8],
+                                           const T (&wyp)[8], const T (&wzm)[8], const T (&wzp)[8],
+                                           const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
+                                           Pred<T, NDIM>& out, T (&du)[8]) {
+  return predict_emit<T, NDIM, true>(w, wxm, wxp, wym, wyp, wzm, wzp, fb, hdt, idx, gam,
+                                     [&](int d, int side, const T (&q)[7]) {
+#pragma unroll
+                                       for (int c = 0; c < 7; ++c) (side ? out.p[d] : out.m[d])[c] = q[c];
+                                     }, du);
 }
 
 template <class T>

@@ -64,6 +64,8 @@ template <class T> struct DevState {
 // element of the face's high-side cell (face index f along d <-> cell f).
 template <class T> struct DevFlux {
   T* f[3][7];
+  // upwinded EMF only: cell-centred reference EMF per component (else null)
+  T* e[3];
 };
 
 // Error flag block in device memory: word 0 = flags, word 1..2 = first bad
@@ -92,11 +94,11 @@ struct WorkQueue {
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 bool xcd, hipStream_t s);
+                 bool xcd, bool upwind_emf, hipStream_t s);
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   bool xcd, hipStream_t s);
+                   bool xcd, bool upwind_emf, hipStream_t s);
 template <class T> void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu);
 
 }  // namespace amr

@@ -18,6 +18,34 @@ __device__ __forceinline__ T edge_emf(const DevFlux<T>& F, int64_t e, const int6
   return T(0.25) * (s2 - s1);
 }
 
+// Upwinded EMF (Gardiner & Stone 2005, J. Comput. Phys. 205, 509) at the
+// same edge: the mean above plus half-cell differences between face values
+// and the cell-centred reference EMF F.e[A] of the four cells around the
+// edge, each difference taken on the upwind side of the mass flux (rotated
+// component 0) through the face it starts from, their mean when that flux is
+// zero.  Names: bS/bN the b-faces below/above the edge along c, cW/cE the
+// c-faces below/above along b, eSW..eNE the cells (b low/high, c low/high).
+template <int A, class T>
+__device__ __forceinline__ T edge_emf_upwind(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  const T bS = -F.f[B][5][e - st[C]], bN = -F.f[B][5][e];
+  const T cW = F.f[C][6][e - st[B]], cE = F.f[C][6][e];
+  const T eSW = F.e[A][e - st[B] - st[C]], eSE = F.e[A][e - st[C]];
+  const T eNW = F.e[A][e - st[B]], eNE = F.e[A][e];
+  auto upw = [](T flux, T lo, T hi) { return flux > T(0) ? lo : (flux < T(0) ? hi : T(0.5) * (lo + hi)); };
+  const T dc_hi = upw(F.f[B][0][e], eNW - cW, eNE - cE);
+  const T dc_lo = upw(F.f[B][0][e - st[C]], cW - eSW, cE - eSE);
+  const T db_hi = upw(F.f[C][0][e], eSE - bS, eNE - bN);
+  const T db_lo = upw(F.f[C][0][e - st[B]], bS - eSW, bN - eNW);
+  return T(0.25) * ((bS + bN) + (cW + cE)) + T(0.25) * ((dc_lo - dc_hi) + (db_lo - db_hi));
+}
+
+template <int A, bool UPWIND, class T>
+__device__ __forceinline__ T emf_at(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
+  if constexpr (UPWIND) return edge_emf_upwind<A>(F, e, st);
+  else return edge_emf<A>(F, e, st);
+}
+
 // Rotated flux component of direction d that carries lab conserved slot s
 // (0 rho, 1..3 momentum, 4 energy, 7 the cell-centred Bz of 2D).
 __device__ __forceinline__ int flux_comp(int s, int d) {

@@ -114,6 +114,7 @@ struct amr_hierarchy {
   // eta-balanced schedule: the grids of a level step anywhere inside the
   // cycles of their step's window (see plan_eta); predicted work per cycle
   int schedule = 0;  // 0: every level at the start of its window; 1: eta-balanced
+  bool upwind_emf = false;  // edge EMF of CT: arithmetic mean or upwinded
   std::vector<LaunchList> eta_lists;
   std::vector<double> cycle_work[2];
   std::map<std::pair<int, int>, LaunchList> grid_lists;  // (grid, band) -> per-grid list
@@ -256,6 +257,7 @@ void validate(const amr_params* p, const amr_grid* grids, int ngrids) {
   if (p->nlevels < 1 || p->nlevels > 12) throw Error(AMR_EINVAL, "nlevels must be in [1, 12]");
   if (p->nlevels > 1 && p->ratio != 2) throw Error(AMR_EUNSUPPORTED, "only refinement ratio 2 is implemented");
   if (p->ratio < 2) throw Error(AMR_EINVAL, "ratio must be >= 2");
+  if (p->emf != AMR_EMF_MEAN && p->emf != AMR_EMF_UPWIND) throw Error(AMR_EINVAL, "emf must be 0 or 1");
   if (p->dtype != AMR_F32 && p->dtype != AMR_F64) throw Error(AMR_EINVAL, "dtype must be AMR_F32 or AMR_F64");
   if (p->ghost < 2) throw Error(AMR_EINVAL, "ghost width must be >= 2");
   if (p->nlevels > 1 && p->ghost < 2 * p->ratio)
@@ -1106,6 +1108,7 @@ template <class T> DevFlux<T> dflux(const amr_hierarchy* h, void* ws) {
   const int64_t stride = h->total_elems * (int64_t)sizeof(T);
   for (int d = 0; d < 3; ++d)
     for (int q = 0; q < 7; ++q) F.f[d][q] = (T*)(base + (int64_t)(d * 7 + q) * stride);
+  for (int a = 0; a < 3; ++a) F.e[a] = h->upwind_emf ? (T*)(base + (int64_t)(21 + a) * stride) : nullptr;
   return F;
 }
 
@@ -1139,11 +1142,11 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
-                 h->d_queue, h->persistent ? h->flux_pblocks : 0, h->xcd_chunks, s);
+                 h->d_queue, h->persistent ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
   launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, h->d_queue,
-                   h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, s);
+                   h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
   if (timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
@@ -1164,7 +1167,7 @@ void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws
     T* freg = (T*)((char*)ws + t.reg_off);
     T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
     launch_registers<T>(h->ndim, h->d_desc, t.d_freg_c, t.n_freg_c, t.d_ereg_c, t.n_ereg_c, F, freg, ereg, t.nfreg,
-                        t.nereg, 0, dt0, div, s);
+                        t.nereg, 0, dt0, div, h->upwind_emf, s);
     HIPCHK(hipGetLastError());
   }
   if (l >= 1) {
@@ -1172,7 +1175,7 @@ void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws
     T* freg = (T*)((char*)ws + t.reg_off);
     T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
     launch_registers<T>(h->ndim, h->d_desc, t.d_freg_f, t.n_freg_f, t.d_ereg_f, t.n_ereg_f, F, freg, ereg, t.nfreg,
-                        t.nereg, 1 + k % h->R, dt0, div, s);
+                        t.nereg, 1 + k % h->R, dt0, div, h->upwind_emf, s);
     HIPCHK(hipGetLastError());
   }
 }
@@ -1312,7 +1315,8 @@ amr_hierarchy* build_hierarchy(const amr_params* p, const amr_grid* grids, int32
     }
     h->total_elems = off;
     if (off >= ((int64_t)1 << 31)) throw Error(AMR_EUNSUPPORTED, "hierarchy exceeds 2^31 elements per pool");
-    h->flux_bytes = 21 * off * (int64_t)h->esize;
+    h->upwind_emf = p->emf == AMR_EMF_UPWIND;
+    h->flux_bytes = (h->upwind_emf ? 24 : 21) * off * (int64_t)h->esize;
     h->reg_offset = (h->flux_bytes + 255) / 256 * 256;
     check_nesting(h);
     h->d_desc = dev_upload(h->desc);
@@ -1994,6 +1998,10 @@ extern "C" {
 
 amr_status amr_frozen_workspace(const amr_hierarchy* h, int64_t* bytes) {
   if (!h || !bytes) return AMR_EINVAL;
+  if (h->upwind_emf) {
+    g_last_error = "the frozen-branch forward supports the arithmetic-mean EMF only";
+    return AMR_EUNSUPPORTED;
+  }
   *bytes = frozen_workspace(h);
   return AMR_OK;
 }
@@ -2002,6 +2010,7 @@ amr_status amr_advance_frozen(amr_hierarchy* h, int32_t level, int32_t nsteps, c
                               const amr_state* U_base, amr_state* U_pert, void* workspace, void* stream) {
   try {
     if (!h || !dts || !U_base || !U_pert || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (h->upwind_emf) throw Error(AMR_EUNSUPPORTED, "the frozen-branch forward supports the arithmetic-mean EMF only");
     if (level < 0 || level >= h->nlev) throw Error(AMR_EINVAL, "level out of range");
     if (nsteps < 1) throw Error(AMR_EINVAL, "nsteps must be >= 1");
     for (int k = 0; k < nsteps; ++k)
@@ -2020,6 +2029,7 @@ amr_status amr_advance_frozen(amr_hierarchy* h, int32_t level, int32_t nsteps, c
 amr_status amr_adjoint_workspace(const amr_hierarchy* h, int32_t grid_or_level, int32_t nsteps, int64_t* bytes) {
   try {
     if (!h || !bytes) throw Error(AMR_EINVAL, "null argument");
+    if (h->upwind_emf) throw Error(AMR_EUNSUPPORTED, "the adjoint supports the arithmetic-mean EMF only");
     if (nsteps < 1) throw Error(AMR_EINVAL, "nsteps must be >= 1");
     const int level = adjoint_level(h, grid_or_level);
     *bytes = adjoint_layout(h, level, nsteps).total;
@@ -2034,6 +2044,7 @@ amr_status amr_advance_adjoint(amr_hierarchy* h, int32_t grid_or_level, int32_t 
                                void* stream) {
   try {
     if (!h || !dts || !U_checkpoint || !lambda_inout || !workspace) throw Error(AMR_EINVAL, "null argument");
+    if (h->upwind_emf) throw Error(AMR_EUNSUPPORTED, "the adjoint supports the arithmetic-mean EMF only");
     if (nsteps < 1) throw Error(AMR_EINVAL, "nsteps must be >= 1");
     for (int k = 0; k < nsteps; ++k)
       if (!(dts[k] > 0.0)) throw Error(AMR_EINVAL, "step sizes must be > 0");

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_reg_faces(const FaceRegEntry* __restric
   }
 }
 
-template <class T, int NDIM>
+template <class T, int NDIM, bool UPWIND>
 __global__ __launch_bounds__(256) void k_reg_edges(const EdgeRegEntry* __restrict__ ent, int n,
                                                    const GridDesc* __restrict__ grids, DevFlux<T> F,
                                                    T* __restrict__ reg, int nreg, int slot,
@@ -49,9 +49,9 @@ __global__ __launch_bounds__(256) void k_reg_edges(const EdgeRegEntry* __restric
     T m = T(0);
     for (int i = 0; i < e.n; ++i) {
       T v;
-      if (e.a == 0) v = edge_emf<0>(F, e.e[i], st);
-      else if (e.a == 1) v = edge_emf<1>(F, e.e[i], st);
-      else v = edge_emf<2>(F, e.e[i], st);
+      if (e.a == 0) v = emf_at<0, UPWIND>(F, e.e[i], st);
+      else if (e.a == 1) v = emf_at<1, UPWIND>(F, e.e[i], st);
+      else v = emf_at<2, UPWIND>(F, e.e[i], st);
       m += v;
     }
     reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_restrict(const RestrictEntry* __restric
 template <class T>
 void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
                       DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
-                      double dt_div, hipStream_t s) {
+                      double dt_div, bool upwind_emf, hipStream_t s) {
   if (nf > 0) {
     if (ndim == 3)
       hipLaunchKernelGGL((k_reg_faces<T, 3>), dim3(blocks_for(nf)), dim3(256), 0, s, fe, nf, F, freg, nfreg, slot, dt0,
@@ -141,12 +141,17 @@ void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, i
                          dt_div);
   }
   if (ne > 0) {
-    if (ndim == 3)
-      hipLaunchKernelGGL((k_reg_edges<T, 3>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg,
-                         slot, dt0, dt_div);
-    else
-      hipLaunchKernelGGL((k_reg_edges<T, 2>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg,
-                         slot, dt0, dt_div);
+#define AMR_REG_EDGES(ND, U)                                                                                       \
+  hipLaunchKernelGGL((k_reg_edges<T, ND, U>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg, \
+                     slot, dt0, dt_div)
+    if (ndim == 3) {
+      if (upwind_emf) AMR_REG_EDGES(3, true);
+      else AMR_REG_EDGES(3, false);
+    } else {
+      if (upwind_emf) AMR_REG_EDGES(2, true);
+      else AMR_REG_EDGES(2, false);
+    }
+#undef AMR_REG_EDGES
   }
 }
 
@@ -175,10 +180,10 @@ void launch_sync(int ndim, int R, const GridDesc* grids, const SyncTables& t, co
 }
 
 template void launch_registers<float>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
-                                      DevFlux<float>, float*, float*, int, int, int, const double*, double,
+                                      DevFlux<float>, float*, float*, int, int, int, const double*, double, bool,
                                       hipStream_t);
 template void launch_registers<double>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
-                                       DevFlux<double>, double*, double*, int, int, int, const double*, double,
+                                       DevFlux<double>, double*, double*, int, int, int, const double*, double, bool,
                                        hipStream_t);
 template void launch_sync<float>(int, int, const GridDesc*, const SyncTables&, const float*, const float*,
                                  DevState<float>, DevState<float>, hipStream_t);

@@ -72,7 +72,7 @@ struct SyncTables {
 template <class T>
 void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
                       DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
-                      double dt_div, hipStream_t s);
+                      double dt_div, bool upwind_emf, hipStream_t s);
 
 // Reflux, EMF fix (coarse level state Uc) and restriction (fine Uf -> Uc).
 template <class T>

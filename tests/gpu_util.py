@@ -24,12 +24,12 @@ def normwise_errors(got, want):
 
 
 def uniform_gpu(ic, nsteps, g=2, fill_every=1, dtype="f64", gamma=5.0 / 3.0, cfl=0.4, bc=(0, 0, 0), dts=None,
-                return_state=False):
+                return_state=False, emf=0):
     """Single periodic (or outflow) grid advanced on the GPU through the ABI."""
     import torch
     ndim, n = ic["ndim"], tuple(ic["n"])
     lo = (0,) * ndim
-    H = A.Hierarchy(ndim, n, [(0, lo, n)], ghost=g, dtype=dtype, bc=bc, dx0=ic["dx"], gamma=gamma, cfl=cfl)
+    H = A.Hierarchy(ndim, n, [(0, lo, n)], ghost=g, dtype=dtype, bc=bc, dx0=ic["dx"], gamma=gamma, cfl=cfl, emf=emf)
     U, V = H.new_state(), H.new_state()
     H.load_primitive(U, 0, ic["prim"], ic["b"])
     used = []
@@ -55,12 +55,12 @@ def uniform_gpu(ic, nsteps, g=2, fill_every=1, dtype="f64", gamma=5.0 / 3.0, cfl
     return out, np.array(used), flags
 
 
-def amr_gpu(ndim, N0, L, grids, fields, ncoarse, dtype="f64", mode=0, ghost=4, return_handle=False):
+def amr_gpu(ndim, N0, L, grids, fields, ncoarse, dtype="f64", mode=0, ghost=4, return_handle=False, emf=0):
     """Hierarchy advanced ncoarse coarse steps on the GPU (mode 0 batched,
     1 per-grid serial).  Returns (per-grid interior arrays, dt0 per step,
     error flags)."""
     import torch
-    H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=ghost, dtype=dtype)
+    H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=ghost, dtype=dtype, emf=emf)
     Ua, Ub = H.new_state(), H.new_state()
     for gi, f in enumerate(fields):
         H.load_primitive(Ua, gi, f["prim"], f["b"])
