@@ -372,6 +372,32 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
   retire<PERSIST>(q);
 }
 
+// Upwinded edge EMFs (one thread per (x, y) column of an update tile one
+// column and row wider than the update's, marching its planes): E_x, E_y, E_z
+// of the edges at the low corner of each element (E_z only in 2D).
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_emf(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
+                                             DevFlux<T> F) {
+  const UpdItem item = items[blockIdx.x];
+  const int tw = item.tw, th = 256 / tw;
+  const int tx = (int)threadIdx.x % tw, ty = (int)threadIdx.x / tw;
+  if (ty >= th) return;
+  const GridDesc G = grids[item.grid];
+  const int ehx = G.n[0] + item.gv - 1, ehy = G.n[1] + item.gv - 1;  // last edge index (inclusive)
+  const int cx = item.x0 + tx, cy = item.y0 + ty;
+  if (cx > ehx || cy > ehy) return;
+  const Idx<NDIM> ix(G);
+  const int64_t st[3] = {1, ix.sy, NDIM == 3 ? ix.sz : 0};
+  for (int k = item.z0; k < item.z1; ++k) {
+    const int64_t e = ix(cx, cy, k);
+    if (NDIM == 3) {
+      F.edge[0][e] = edge_emf_upwind<0>(F, e, st);
+      F.edge[1][e] = edge_emf_upwind<1>(F, e, st);
+    }
+    F.edge[2][e] = edge_emf_upwind<2>(F, e, st);
+  }
+}
+
 }  // namespace
 
 template <class T>
@@ -437,6 +463,17 @@ void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int ni
   }
 #undef AMR_UPD_LAUNCH
 }
+
+template <class T>
+void launch_emf(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevFlux<T> F, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (ndim == 3)
+    hipLaunchKernelGGL((k_emf<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, F);
+  else
+    hipLaunchKernelGGL((k_emf<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, F);
+}
+template void launch_emf<float>(int, const GridDesc*, const UpdItem*, int, DevFlux<float>, hipStream_t);
+template void launch_emf<double>(int, const GridDesc*, const UpdItem*, int, DevFlux<double>, hipStream_t);
 
 // Resident 256-thread blocks per CU of each kernel (for persistent launches).
 template <class T>

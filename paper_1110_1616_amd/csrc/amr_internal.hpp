@@ -64,8 +64,10 @@ template <class T> struct DevState {
 // element of the face's high-side cell (face index f along d <-> cell f).
 template <class T> struct DevFlux {
   T* f[3][7];
-  // upwinded EMF only: cell-centred reference EMF per component (else null)
+  // upwinded EMF only (else null): cell-centred reference EMF per component,
+  // and the edge EMFs computed from it once per edge
   T* e[3];
+  T* edge[3];
 };
 
 // Error flag block in device memory: word 0 = flags, word 1..2 = first bad
@@ -99,6 +101,10 @@ template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
                    bool xcd, bool upwind_emf, hipStream_t s);
+// Upwinded edge EMFs of every edge the update reads (items: the update tiles
+// of the same grids, one column and row wider).
+template <class T>
+void launch_emf(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevFlux<T> F, hipStream_t s);
 template <class T> void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu);
 
 }  // namespace amr

@@ -40,9 +40,11 @@ __device__ __forceinline__ T edge_emf_upwind(const DevFlux<T>& F, int64_t e, con
   return T(0.25) * ((bS + bN) + (cW + cE)) + T(0.25) * ((dc_lo - dc_hi) + (db_lo - db_hi));
 }
 
+// Edge EMF as the update and the registers read it: the mean from the face
+// fluxes, or the upwinded value stored per edge by the EMF kernel.
 template <int A, bool UPWIND, class T>
 __device__ __forceinline__ T emf_at(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
-  if constexpr (UPWIND) return edge_emf_upwind<A>(F, e, st);
+  if constexpr (UPWIND) return F.edge[A][e];
   else return edge_emf<A>(F, e, st);
 }
 

@@ -11,6 +11,7 @@
 #include <exception>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -67,7 +68,7 @@ struct ListRef {
 };
 
 struct LaunchList {
-  ListRef flux, upd;
+  ListRef flux, upd, emf;
 };
 
 }  // namespace
@@ -91,6 +92,8 @@ struct amr_hierarchy {
   GridDesc* d_desc = nullptr;
   FluxItem* d_fitems = nullptr;
   UpdItem* d_uitems = nullptr;
+  UpdItem* d_eitems = nullptr;  // upwinded EMF only: edge-EMF tiles
+  std::vector<UpdItem> h_eitems;
   std::vector<FluxItem> h_fitems;
   std::vector<UpdItem> h_uitems;
   int4* d_cfl = nullptr;
@@ -168,6 +171,7 @@ struct amr_hierarchy {
     (void)hipFree(d_desc);
     (void)hipFree(d_fitems);
     (void)hipFree(d_uitems);
+    (void)hipFree(d_eitems);
     (void)hipFree(d_cfl);
     (void)hipFree(d_err);
     (void)hipFree(d_queue);
@@ -360,13 +364,33 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
         it.z1 = h->ndim == 3 ? std::min(z0 + zc, uzhi) : 1;
         ul.push_back(it);
       }
+  if (!h->upwind_emf) return;
+  // upwinded edge EMFs: the update's planes, one more column and row (the
+  // update reads the edges at e and e + 1 along both transverse axes)
+  const int etw = pick_tile(uh[0] - ul0 + 2, uh[1] - ul0 + 2, 0, h->tile_policy), eth = 256 / etw;
+  check_tile(etw);
+  for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? zc : 1))
+    for (int y0 = ul0; y0 <= uh[1] + 1; y0 += eth)
+      for (int x0 = ul0; x0 <= uh[0] + 1; x0 += etw) {
+        UpdItem it{};
+        it.tw = etw;
+        it.grid = gi;
+        it.gv = gv;
+        it.x0 = x0;
+        it.y0 = y0;
+        it.z0 = z0;
+        it.z1 = h->ndim == 3 ? std::min(z0 + zc, uzhi) : 1;
+        h->h_eitems.push_back(it);
+      }
 }
 
 LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& grid_bands) {
   LaunchList L;
   L.flux.off = (int)h->h_fitems.size();
   L.upd.off = (int)h->h_uitems.size();
+  L.emf.off = (int)h->h_eitems.size();
   for (auto& gb : grid_bands) add_grid_items(h, gb.first, gb.second, h->h_fitems, h->h_uitems);
+  L.emf.n = (int)h->h_eitems.size() - L.emf.off;
   L.flux.n = (int)h->h_fitems.size() - L.flux.off;
   L.upd.n = (int)h->h_uitems.size() - L.upd.off;
   return L;
@@ -498,6 +522,7 @@ void build_lists(amr_hierarchy* h) {
   }
   h->d_fitems = dev_upload(h->h_fitems);
   h->d_uitems = dev_upload(h->h_uitems);
+  h->d_eitems = dev_upload(h->h_eitems);
   // CFL items: (grid, interior plane, first row, rows), about 1k cells each
   std::vector<int4> cf;
   for (int gi = 0; gi < (int)h->grids.size(); ++gi) {
@@ -1108,7 +1133,10 @@ template <class T> DevFlux<T> dflux(const amr_hierarchy* h, void* ws) {
   const int64_t stride = h->total_elems * (int64_t)sizeof(T);
   for (int d = 0; d < 3; ++d)
     for (int q = 0; q < 7; ++q) F.f[d][q] = (T*)(base + (int64_t)(d * 7 + q) * stride);
-  for (int a = 0; a < 3; ++a) F.e[a] = h->upwind_emf ? (T*)(base + (int64_t)(21 + a) * stride) : nullptr;
+  for (int a = 0; a < 3; ++a) {
+    F.e[a] = h->upwind_emf ? (T*)(base + (int64_t)(21 + a) * stride) : nullptr;
+    F.edge[a] = h->upwind_emf ? (T*)(base + (int64_t)(24 + a) * stride) : nullptr;
+  }
   return F;
 }
 
@@ -1145,6 +1173,12 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
                  h->d_queue, h->persistent ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
+  if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+    if (h->upwind_emf) {
+      launch_emf<T>(h->ndim, h->d_desc, h->d_eitems + L.emf.off, L.emf.n, F, s);
+      HIPCHK(hipGetLastError());
+    }
+  }
   launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, h->d_queue,
                    h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
@@ -1316,7 +1350,7 @@ amr_hierarchy* build_hierarchy(const amr_params* p, const amr_grid* grids, int32
     h->total_elems = off;
     if (off >= ((int64_t)1 << 31)) throw Error(AMR_EUNSUPPORTED, "hierarchy exceeds 2^31 elements per pool");
     h->upwind_emf = p->emf == AMR_EMF_UPWIND;
-    h->flux_bytes = (h->upwind_emf ? 24 : 21) * off * (int64_t)h->esize;
+    h->flux_bytes = (h->upwind_emf ? 27 : 21) * off * (int64_t)h->esize;
     h->reg_offset = (h->flux_bytes + 255) / 256 * 256;
     check_nesting(h);
     h->d_desc = dev_upload(h->desc);
@@ -1703,6 +1737,9 @@ void rebuild_lists(amr_hierarchy* h) {
   h->graph_exec[0] = h->graph_exec[1] = nullptr;
   HIPCHK(hipFree(h->d_fitems));
   HIPCHK(hipFree(h->d_uitems));
+  HIPCHK(hipFree(h->d_eitems));
+  h->d_eitems = nullptr;
+  h->h_eitems.clear();
   HIPCHK(hipFree(h->d_cfl));
   h->d_fitems = nullptr;
   h->d_uitems = nullptr;
