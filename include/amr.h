@@ -451,7 +451,8 @@ amr_status amr_flag_cells(amr_hierarchy* h, int32_t level, amr_state* U_level, a
  * the new level+1 boxes (times R), then the grids of levels >= level+2 in
  * their order; *nout = the count (AMR_EINVAL with *nout set when capacity
  * is too small).  AMR_EUNSUPPORTED when the level's grids span more than
- * 2^28 cells of index space. */
+ * 2^28 cells of index space.  With no flagged cell and no level+2 grids the
+ * new level+1 is empty, which amr_create() rejects (levels need grids). */
 amr_status amr_regrid(amr_hierarchy* h, int32_t level, amr_state* U_level, amr_state* U_parent,
                       const amr_regrid_params* params, amr_grid* out, int32_t capacity, int32_t* nout, void* stream);
 
