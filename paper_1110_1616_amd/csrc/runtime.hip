@@ -228,15 +228,30 @@ struct LevelIndex {
     }
     return true;
   }
-  // Grid whose interior holds cell c (already wrapped), or -1.
+  bool holds(int gi, const int (&c)[3]) const {
+    if (gi < 0 || gi >= (int)h->grids.size()) return false;
+    const amr_grid& G = h->grids[gi];
+    if (G.level != level) return false;
+    for (int d = 0; d < 3; ++d)
+      if (c[d] < G.lo[d] || c[d] >= G.hi[d]) return false;
+    return true;
+  }
+  // Grid whose interior holds cell c (already wrapped), or -1.  Lookups come
+  // in runs from one grid, so each thread first tries its last two hits (the
+  // grids of a level are disjoint: a grid of this level holding c is the
+  // answer, whatever lookup produced it).
   int find_cell(const int (&c)[3]) const {
+    thread_local int memo[2] = {-1, -1};
+    thread_local unsigned turn = 0;
+    for (int m = 0; m < 2; ++m)
+      if (holds(memo[m], c)) return memo[m];
     auto it = buckets.find(key(floordiv(c[0], B), floordiv(c[1], B), floordiv(c[2], B)));
     if (it == buckets.end()) return -1;
     for (int gi : it->second) {
-      const amr_grid& G = h->grids[gi];
-      bool in = true;
-      for (int d = 0; d < 3; ++d) in = in && c[d] >= G.lo[d] && c[d] < G.hi[d];
-      if (in) return gi;
+      if (holds(gi, c)) {
+        memo[turn++ & 1] = gi;
+        return gi;
+      }
     }
     return -1;
   }
@@ -753,28 +768,37 @@ void build_fill_maps(amr_hierarchy* h) {
     }
     };
     parallel_for(lg.size(), one_grid);
-    std::vector<CopyEntry> cp[4];
-    std::vector<ProlongEntry> pc, pf;
-    for (GridMaps& m : per) {
-      for (int c = 0; c < 4; ++c) cp[c].insert(cp[c].end(), m.cp[c].begin(), m.cp[c].end());
-      pc.insert(pc.end(), m.pc.begin(), m.pc.end());
-      pf.insert(pf.end(), m.pf.begin(), m.pf.end());
-      m = GridMaps();
+    // concatenate: copies class by class (cells, x-, y-, z-faces), each in
+    // grid order; prolongations in grid order
+    size_t ncp[4] = {0, 0, 0, 0}, npc = 0, npf = 0;
+    for (const GridMaps& m : per) {
+      for (int c = 0; c < 4; ++c) ncp[c] += m.cp[c].size();
+      npc += m.pc.size();
+      npf += m.pf.size();
     }
     std::vector<CopyEntry> all;
+    all.reserve(ncp[0] + ncp[1] + ncp[2] + ncp[3]);
     int4 cls = make_int4(0, 0, 0, 0);
     for (int c = 0; c < 4; ++c) {
-      all.insert(all.end(), cp[c].begin(), cp[c].end());
+      for (const GridMaps& m : per) all.insert(all.end(), m.cp[c].begin(), m.cp[c].end());
       int v = (int)all.size();
       if (c == 0) cls.x = v;
       if (c == 1) cls.y = v;
       if (c == 2) cls.z = v;
       if (c == 3) cls.w = v;
     }
+    std::vector<ProlongEntry> pc, pf;
+    pc.reserve(npc);
+    pf.reserve(npf);
+    for (GridMaps& m : per) {
+      pc.insert(pc.end(), m.pc.begin(), m.pc.end());
+      pf.insert(pf.end(), m.pf.begin(), m.pf.end());
+      m = GridMaps();
+    }
     h->copy_cls[l] = cls;
     h->n_copy[l] = (int)all.size();
-    h->h_copy[l] = all;
     h->d_copy[l] = dev_upload(all);
+    h->h_copy[l] = std::move(all);
     h->n_pcell[l] = (int)pc.size();
     h->n_pface[l] = (int)pf.size();
     h->d_pcell[l] = dev_upload(pc);
