@@ -47,10 +47,11 @@ def cpu_model():
 
 
 def kernel_source_digest():
-    """sha256 over the sources that define the flux kernel's memory traffic."""
+    """sha256 over the sources that define the flux kernel's memory traffic
+    (the kernels and the host code that builds their work lists)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp"):
+    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp", "runtime.hip"):
         with open(os.path.join(ROOT, "paper_1110_1616_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -176,7 +177,7 @@ def amr_workload(args, deep=False):
     for (l, lo, hi) in grids:
         n = [hi[a] - lo[a] for a in range(3)]
         for k in range(2 ** l):
-            gv = 4 if l == 0 else 4 - 2 * (k % 2)
+            gv = 2 if l == 0 else 4 - 2 * (k % 2)
             fl += flux_kernel_flops(3, n, gv)
     st = {"par": 0}
     stream = torch.cuda.Stream()

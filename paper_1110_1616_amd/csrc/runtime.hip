@@ -415,6 +415,14 @@ int64_t cells_of(const amr_grid& G) {
   return (int64_t)(G.hi[0] - G.lo[0]) * (G.hi[1] - G.lo[1]) * (G.hi[2] - G.lo[2]);
 }
 
+// Valid band a level-l grid steps from at its k-th step of a coarse step.
+// Levels above 0 are filled once per parent step with the full band g = 2R
+// and consume 2 cells per substep.  Level 0 is refilled before each of its
+// steps and nothing reads its band after the step, so it steps from band 2
+// (a step needs 2 band cells; its interior is the same for any band >= 2,
+// since a cell depends only on data within 2 cells).
+int step_band(const amr_hierarchy* h, int l, int k) { return l == 0 ? 2 : h->g - 2 * (k % h->R); }
+
 // Predicted cost of one step of grid gi from band gv: the cells of the
 // flux kernel's computed region.
 double step_work(const amr_hierarchy* h, int gi, int gv) {
@@ -446,7 +454,7 @@ void plan_eta(const amr_hierarchy* h, int schedule, std::vector<std::vector<int>
     for (int gi : h->level_grids[l]) cyc[gi].assign(nsteps, 0);
     for (int k = 0; k < nsteps; ++k) {
       const int c0 = k * span;
-      const int gv = l == 0 ? h->g : h->g - 2 * (k % R);
+      const int gv = step_band(h, l, k);
       std::vector<std::pair<double, int>> w;
       double tot = 0.0;
       for (int gi : h->level_grids[l]) {
@@ -488,7 +496,7 @@ void build_lists(amr_hierarchy* h) {
       const int span = ipow(h->R, L - 1 - l);
       if (c % span) continue;
       const int k = c / span;  // substep index of level l in this coarse step
-      const int gv = l == 0 ? h->g : h->g - 2 * (k % h->R);
+      const int gv = step_band(h, l, k);
       std::vector<int> gl = h->level_grids[l];
       std::stable_sort(gl.begin(), gl.end(),
                        [&](int a, int b) { return cells_of(h->grids[a]) > cells_of(h->grids[b]); });
@@ -508,7 +516,7 @@ void build_lists(amr_hierarchy* h) {
       for (int l = L - 1; l >= 0; --l) {
         const int span = ipow(h->R, L - 1 - l);
         const int k = c / span;
-        const int gv = l == 0 ? h->g : h->g - 2 * (k % h->R);
+        const int gv = step_band(h, l, k);
         std::vector<int> gl;
         for (int gi : h->level_grids[l])
           if (cyc[gi][k] == c) gl.push_back(gi);
@@ -1303,7 +1311,7 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
   } else {
     std::function<void(int, int)> cyc = [&](int l, int k) {
       if (l + 1 < L) do_fill<T>(h, l + 1, AMR_FILL_FULL, cur(l + 1), cur(l), s);
-      const int band = l == 0 ? h->g : h->g - 2 * (k % R);
+      const int band = step_band(h, l, k);
       for (int gi : h->level_grids[l]) run_list<T>(h, h->grid_lists.at({gi, band}), Ua, Ub, par, dt0, ws, s);
       write_registers<T>(h, l, k, dt0, ws, s);
       par ^= 1u << l;

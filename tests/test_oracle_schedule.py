@@ -67,7 +67,7 @@ def test_plan_windows_and_bounds(L, seed):
     for l in range(L - 1, -1, -1):
         span = R ** (L - 1 - l)
         for k in range(R ** l):
-            gv = 4 if l == 0 else 4 - 2 * (k % R)
+            gv = 2 if l == 0 else 4 - 2 * (k % R)
             gl = [gi for gi, g in enumerate(grids) if g[0] == l]
             ws = [work(gi, gv) for gi in gl]
             win = slice(k * span, (k + 1) * span)
