@@ -106,6 +106,11 @@ struct amr_hierarchy {
   std::vector<CopyEntry*> d_copy;
   std::vector<int> n_copy;
   std::vector<int4> copy_cls;
+  // the copy entries within 2 cells of each interior: the same-level fills
+  // before a step from band 2 (level 0, and the refresh before substeps k >= 1)
+  std::vector<CopyEntry*> d_copy2;
+  std::vector<int> n_copy2;
+  std::vector<int4> copy2_cls;
   std::vector<ProlongEntry*> d_pcell, d_pface;
   std::vector<int> n_pcell, n_pface;
 
@@ -176,6 +181,7 @@ struct amr_hierarchy {
     (void)hipFree(d_err);
     (void)hipFree(d_queue);
     for (auto p : d_copy) (void)hipFree(p);
+    for (auto p : d_copy2) (void)hipFree(p);
     for (auto p : d_pcell) (void)hipFree(p);
     for (auto p : d_pface) (void)hipFree(p);
     for (auto& s : sync) s.release();
@@ -620,6 +626,9 @@ void build_fill_maps(amr_hierarchy* h) {
   for (int l = 0; l < h->nlev; ++l) idx[l].build(h, l);
   h->d_copy.assign(h->nlev, nullptr);
   h->n_copy.assign(h->nlev, 0);
+  h->d_copy2.assign(h->nlev, nullptr);
+  h->n_copy2.assign(h->nlev, 0);
+  h->copy2_cls.assign(h->nlev, make_int4(0, 0, 0, 0));
   h->copy_cls.assign(h->nlev, make_int4(0, 0, 0, 0));
   h->h_copy.assign(h->nlev, {});
   h->d_pcell.assign(h->nlev, nullptr);
@@ -633,6 +642,7 @@ void build_fill_maps(amr_hierarchy* h) {
     // its own lists, concatenated in grid order afterwards
     struct GridMaps {
       std::vector<CopyEntry> cp[4];
+      std::vector<CopyEntry> cp2[4];  // the entries within 2 cells of the interior
       std::vector<ProlongEntry> pc, pf;
     };
     const std::vector<int>& lg = h->level_grids[l];
@@ -640,6 +650,7 @@ void build_fill_maps(amr_hierarchy* h) {
     auto one_grid = [&](size_t slot) {
     const int gi = lg[slot];
     std::vector<CopyEntry>(&cp)[4] = per[slot].cp;
+    std::vector<CopyEntry>(&cp2)[4] = per[slot].cp2;
     std::vector<ProlongEntry>& pc = per[slot].pc;
     std::vector<ProlongEntry>& pf = per[slot].pf;
     {
@@ -713,6 +724,13 @@ void build_fill_maps(amr_hierarchy* h) {
                 const amr_grid& SG = h->grids[src_grid];
                 const int64_t src = elem(S, nd, sp[0] - SG.lo[0], sp[1] - SG.lo[1], sp[2] - SG.lo[2]);
                 cp[cls].push_back(CopyEntry{(int32_t)dst, (int32_t)src});
+                const int x2[3] = {i, j, k};
+                bool near2 = true;
+                for (int a = 0; a < nd; ++a) {
+                  const int top = G.n[a] + ((cls == 1 + a) ? 2 : 1);
+                  near2 = near2 && x2[a] >= -2 && x2[a] <= top;
+                }
+                if (near2) cp2[cls].push_back(CopyEntry{(int32_t)dst, (int32_t)src});
                 continue;
               }
               if (l == 0) throw Error(AMR_EINVAL, "level 0 does not tile the domain (uncovered band element)");
@@ -795,6 +813,19 @@ void build_fill_maps(amr_hierarchy* h) {
       if (c == 2) cls.z = v;
       if (c == 3) cls.w = v;
     }
+    std::vector<CopyEntry> all2;
+    int4 cls2 = make_int4(0, 0, 0, 0);
+    for (int c = 0; c < 4; ++c) {
+      for (const GridMaps& m : per) all2.insert(all2.end(), m.cp2[c].begin(), m.cp2[c].end());
+      int v = (int)all2.size();
+      if (c == 0) cls2.x = v;
+      if (c == 1) cls2.y = v;
+      if (c == 2) cls2.z = v;
+      if (c == 3) cls2.w = v;
+    }
+    h->copy2_cls[l] = cls2;
+    h->n_copy2[l] = (int)all2.size();
+    h->d_copy2[l] = dev_upload(all2);
     std::vector<ProlongEntry> pc, pf;
     pc.reserve(npc);
     pf.reserve(npf);
@@ -1257,8 +1288,12 @@ void do_sync(amr_hierarchy* h, int f, const amr_state* Uf, amr_state* Uc, void* 
 }
 
 template <class T>
-void do_fill(amr_hierarchy* h, int level, int mode, amr_state* Ul, const amr_state* Up, hipStream_t s) {
-  launch_copy<T>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<T>(Ul), s);
+void do_fill(amr_hierarchy* h, int level, int mode, amr_state* Ul, const amr_state* Up, hipStream_t s,
+             bool band2_only = false) {
+  if (band2_only)
+    launch_copy<T>(h->ndim, h->d_copy2[level], h->n_copy2[level], h->copy2_cls[level], dstate<T>(Ul), s);
+  else
+    launch_copy<T>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<T>(Ul), s);
   if (mode == AMR_FILL_FULL && level > 0)
     launch_prolong<T>(h->ndim, h->d_pcell[level], h->n_pcell[level], h->d_pface[level], h->n_pface[level], h->d_desc,
                       dstate<T>(Up), dstate<T>(Ul), phys(h), s);
@@ -1282,7 +1317,8 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
   const int L = h->nlev, R = h->R;
   auto cur = [&](int l) { return ((par >> l) & 1u) ? Ub : Ua; };
   do_dt<T>(h, Ua, Ub, par, dt0, s);
-  do_fill<T>(h, 0, AMR_FILL_SAME_LEVEL, cur(0), cur(0), s);
+  // level 0 steps from band 2 (step_band): its same-level fill copies that much
+  do_fill<T>(h, 0, AMR_FILL_SAME_LEVEL, cur(0), cur(0), s, true);
   if (mode == 0) {
     const int ncyc = ipow(R, L - 1);
     const std::vector<LaunchList>& lists = h->schedule == 1 ? h->eta_lists : h->cycle_lists;
@@ -1292,7 +1328,9 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
         const int span = ipow(R, L - 1 - l);
         if (c % span) continue;
         const int k = c / span;
-        do_fill<T>(h, l, (k % R == 0) ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s);
+        // the refresh before substeps k >= 1 feeds a step from band 2
+        if (k % R == 0) do_fill<T>(h, l, AMR_FILL_FULL, cur(l), cur(l - 1), s);
+        else do_fill<T>(h, l, AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s, step_band(h, l, k) == 2);
       }
       run_list<T>(h, lists[c], Ua, Ub, par, dt0, ws, s);
       // levels whose window ends here: every grid has stepped; registers,
@@ -1317,7 +1355,7 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
       par ^= 1u << l;
       if (l + 1 < L) {
         for (int kk = 0; kk < R; ++kk) {
-          if (kk > 0) do_fill<T>(h, l + 1, AMR_FILL_SAME_LEVEL, cur(l + 1), cur(l), s);
+          if (kk > 0) do_fill<T>(h, l + 1, AMR_FILL_SAME_LEVEL, cur(l + 1), cur(l), s, step_band(h, l + 1, kk) == 2);
           cyc(l + 1, kk);
         }
         do_sync<T>(h, l + 1, cur(l + 1), cur(l), ws, s);
