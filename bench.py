@@ -373,8 +373,8 @@ def main():
     ap.add_argument("--regrid-max-box", type=int, default=32,
                     help="largest box extent of the measured regrid, in level-1 cells")
     ap.add_argument("--launch-config", default=None,
-                    help="tile_policy,zchunk,launch_mode: set this launch configuration instead of autotuning "
-                         "(launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD)")
+                    help="tile_policy,zchunk,launch_mode[,update_zchunk]: set this launch configuration instead "
+                         "of autotuning (launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")
@@ -427,15 +427,18 @@ def main():
     torch.cuda.synchronize()
     tuned = None
     if args.launch_config:
-        pol, zc, per = (int(v) for v in args.launch_config.split(","))
-        H.set_launch_config(pol, zc, per)
-        tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "launch_mode": per}, "set_by": "--launch-config"}
+        vals = [int(v) for v in args.launch_config.split(",")]
+        pol, zc, per = vals[:3]
+        uz = vals[3] if len(vals) > 3 else None
+        H.set_launch_config(pol, zc, per, uz)
+        tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "launch_mode": per,
+                            "update_zchunk": A.amr_get_update_zchunk(H.h)}, "set_by": "--launch-config"}
     elif W.get("tune") and not args.no_autotune:
         chosen, table = W["tune"]()
         torch.cuda.synchronize()
         tuned = {"chosen": {"tile_policy": table[chosen][0], "zchunk": table[chosen][1],
-                            "launch_mode": table[chosen][2]},
-                 "candidates_ms": [[t[0], t[1], t[2], round(t[3], 4)] for t in table]}
+                            "launch_mode": table[chosen][2], "update_zchunk": table[chosen][4]},
+                 "candidates_ms": [[t[0], t[1], t[2], t[4], round(t[3], 4)] for t in table]}
         for _ in range(2):
             W["eager"]()
         torch.cuda.synchronize()

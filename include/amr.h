@@ -318,19 +318,30 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
 amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
 
-#define AMR_TUNE_CANDIDATES 32
+/* Planes along z per work item of the update (and of the upwinded-EMF edge
+ * kernel) in 3-D, separate from the flux kernel's z-chunk (default 2; the
+ * update keeps nothing between planes, so short items spread the work over
+ * more blocks).  Results do not depend on it, bit for bit.  zchunk in
+ * [1, 4096], else AMR_EINVAL.  Changing it rebuilds the work lists and drops
+ * captured graphs. */
+amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk);
+amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk);
+
+#define AMR_TUNE_CANDIDATES 36
 
 typedef struct {
-  int32_t tile_policy, zchunk, launch_mode, pad;
+  int32_t tile_policy, zchunk, launch_mode, update_zchunk;
   double ms; /* reps passes over every launch cycle's batched advance */
 } amr_tune_entry;
 
 /* Autotuner of the batched advance: fills every level's band (FULL, coarse
  * to fine) and computes dt0 (both redone by the next coarse step), then
- * times each of the AMR_TUNE_CANDIDATES configurations (tile_policy x zchunk
- * in {8, 16, 32, 64} x launch_mode in [0, 3]) over `reps` passes of every
- * launch cycle's batched advance, reading each level's current buffer
- * (parity) and writing the other one, and keeps the fastest.  The state the
+ * times the 32 configurations tile_policy x zchunk in {8, 16, 32, 64} x
+ * launch_mode in [0, 3] (entries 0..31, under the current update z-chunk),
+ * keeps the fastest, and under it times the update z-chunks {1, 2, 4, 8}
+ * (entries 32..35), each over `reps` passes of every launch cycle's batched
+ * advance, reading each level's current buffer (parity) and writing the
+ * other one, and keeps the fastest of all 36.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */

@@ -41,7 +41,7 @@ class amr_state(C.Structure):
 
 
 class amr_tune_entry(C.Structure):
-    _fields_ = [("tile_policy", C.c_int32), ("zchunk", C.c_int32), ("launch_mode", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("tile_policy", C.c_int32), ("zchunk", C.c_int32), ("launch_mode", C.c_int32), ("update_zchunk", C.c_int32),
                 ("ms", C.c_double)]
 
 
@@ -93,6 +93,8 @@ def lib():
                                          C.POINTER(amr_state), _VP, _VP]
         L.amr_set_launch_config.argtypes = [_VP, C.c_int32, C.c_int32, C.c_int32]
         L.amr_get_launch_config.argtypes = [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.amr_set_update_zchunk.argtypes = [_VP, C.c_int32]
+        L.amr_get_update_zchunk.argtypes = [_VP, C.POINTER(C.c_int32)]
         L.amr_autotune.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP, C.c_int32,
                                    C.POINTER(amr_tune_entry), C.POINTER(C.c_int32), _VP]
         L.amr_get_error_flags.argtypes = [_VP, C.POINTER(C.c_uint32), C.POINTER(C.c_int64)]
@@ -283,16 +285,26 @@ def amr_get_launch_config(h):
     return a.value, b.value, c.value
 
 
-TUNE_CANDIDATES = 32
+def amr_set_update_zchunk(h, zchunk):
+    _check(lib().amr_set_update_zchunk(h, int(zchunk)), "amr_set_update_zchunk")
+
+
+def amr_get_update_zchunk(h):
+    a = C.c_int32()
+    _check(lib().amr_get_update_zchunk(h, C.byref(a)), "amr_get_update_zchunk")
+    return a.value
+
+
+TUNE_CANDIDATES = 36
 
 
 def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):
-    """Returns (chosen index, [(tile_policy, zchunk, launch_mode, ms), ...])."""
+    """Returns (chosen index, [(tile_policy, zchunk, launch_mode, ms, update_zchunk), ...])."""
     res = (amr_tune_entry * TUNE_CANDIDATES)()
     ch = C.c_int32()
     _check(lib().amr_autotune(h, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws), reps, res, C.byref(ch),
                               _stream()), "amr_autotune")
-    return ch.value, [(r.tile_policy, r.zchunk, r.launch_mode, r.ms) for r in res]
+    return ch.value, [(r.tile_policy, r.zchunk, r.launch_mode, r.ms, r.update_zchunk) for r in res]
 
 
 def amr_get_error_flags(h):
@@ -507,8 +519,10 @@ class Hierarchy:
     def autotune(self, Ua, Ub, parity, reps=3):
         return amr_autotune(self.h, Ua.c, Ub.c, parity, self.dt0, self.ws, reps)
 
-    def set_launch_config(self, tile_policy, zchunk, launch_mode):
+    def set_launch_config(self, tile_policy, zchunk, launch_mode, update_zchunk=None):
         amr_set_launch_config(self.h, tile_policy, zchunk, launch_mode)
+        if update_zchunk is not None:
+            amr_set_update_zchunk(self.h, update_zchunk)
 
     def current(self, Ua, Ub, parity, level):
         return Ub if (parity >> level) & 1 else Ua

@@ -144,6 +144,7 @@ struct amr_hierarchy {
   std::vector<FlagItem*> d_flag_items;
   std::vector<int> n_flag_items;
   int zchunk = 16;
+  int upd_zchunk = 2;  // planes per update / edge-EMF work item (the update prefers short ones)
   int tile_policy = 1;  // 0: 16 x 16 tiles; 1: per-grid width with the fewest tiles
   bool persistent = false;     // persistent launches popping d_queue, or one block per item
   bool xcd_chunks = false;     // item lists cut into one contiguous chunk per XCD
@@ -372,7 +373,8 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   const int uzhi = h->ndim == 3 ? uh[2] + 1 : 1;
   const int utw = pick_tile(uh[0] - ul0 + 1, uh[1] - ul0 + 1, 0, h->tile_policy), uth = 256 / utw;
   check_tile(utw);
-  for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? zc : 1))
+  const int uzc = h->upd_zchunk;
+  for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? uzc : 1))
     for (int y0 = ul0; y0 <= uh[1]; y0 += uth)
       for (int x0 = ul0; x0 <= uh[0]; x0 += utw) {
         UpdItem it{};
@@ -382,7 +384,7 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
         it.x0 = x0;
         it.y0 = y0;
         it.z0 = z0;
-        it.z1 = h->ndim == 3 ? std::min(z0 + zc, uzhi) : 1;
+        it.z1 = h->ndim == 3 ? std::min(z0 + uzc, uzhi) : 1;
         ul.push_back(it);
       }
   if (!h->upwind_emf) return;
@@ -390,7 +392,7 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   // update reads the edges at e and e + 1 along both transverse axes)
   const int etw = pick_tile(uh[0] - ul0 + 2, uh[1] - ul0 + 2, 0, h->tile_policy), eth = 256 / etw;
   check_tile(etw);
-  for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? zc : 1))
+  for (int z0 = uzlo; z0 < uzhi; z0 += (h->ndim == 3 ? uzc : 1))
     for (int y0 = ul0; y0 <= uh[1] + 1; y0 += eth)
       for (int x0 = ul0; x0 <= uh[0] + 1; x0 += etw) {
         UpdItem it{};
@@ -400,7 +402,7 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
         it.x0 = x0;
         it.y0 = y0;
         it.z0 = z0;
-        it.z1 = h->ndim == 3 ? std::min(z0 + zc, uzhi) : 1;
+        it.z1 = h->ndim == 3 ? std::min(z0 + uzc, uzhi) : 1;
         h->h_eitems.push_back(it);
       }
 }
@@ -1824,6 +1826,14 @@ void rebuild_lists(amr_hierarchy* h) {
   build_lists(h);
 }
 
+void set_update_zchunk(amr_hierarchy* h, int zchunk) {
+  if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "update z-chunk must be in [1, 4096]");
+  if (zchunk != h->upd_zchunk) {
+    h->upd_zchunk = zchunk;
+    rebuild_lists(h);
+  }
+}
+
 void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
   if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
@@ -1880,13 +1890,28 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
       for (int mode = 0; mode < 4; ++mode, ++n) {
         set_launch_config(h, pol, zc[zi], mode);
         const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
-        if (out) out[n] = amr_tune_entry{pol, zc[zi], mode, 0, ms};
+        if (out) out[n] = amr_tune_entry{pol, zc[zi], mode, h->upd_zchunk, ms};
         if (best < 0 || ms < best_ms) {
           best = n;
           best_ms = ms;
         }
       }
-  set_launch_config(h, (best >> 4) & 1, zc[(best >> 2) & 3], best & 3);
+  const int bpol = (best >> 4) & 1, bzc = zc[(best >> 2) & 3], bmode = best & 3;
+  set_launch_config(h, bpol, bzc, bmode);
+  // then the update's planes per item, under the kept configuration
+  const int uzc[4] = {1, 2, 4, 8};
+  int ubest = h->upd_zchunk;
+  for (int ui = 0; ui < 4; ++ui, ++n) {
+    set_update_zchunk(h, uzc[ui]);
+    const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
+    if (out) out[n] = amr_tune_entry{bpol, bzc, bmode, uzc[ui], ms};
+    if (ms < best_ms) {
+      best = n;
+      best_ms = ms;
+      ubest = uzc[ui];
+    }
+  }
+  set_update_zchunk(h, ubest);
   return best;
 }
 
@@ -2265,6 +2290,22 @@ amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t 
   } catch (const std::exception& e) {
     return fail(e);
   }
+}
+
+amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk) {
+  try {
+    if (!h) throw Error(AMR_EINVAL, "null argument");
+    set_update_zchunk(h, zchunk);
+    return AMR_OK;
+  } catch (const std::exception& e) {
+    return fail(e);
+  }
+}
+
+amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk) {
+  if (!h || !zchunk) return AMR_EINVAL;
+  *zchunk = h->upd_zchunk;
+  return AMR_OK;
 }
 
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode) {

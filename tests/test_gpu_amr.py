@@ -136,19 +136,22 @@ def test_graph_replay_matches_eager_every_replay():
 
 @pytest.mark.parametrize("key", ["3d", "2d"])
 def test_every_launch_configuration_gives_identical_results(key):
-    """Tile policy, z-chunk, persistent vs one-block-per-item launches and XCD
-    chunking only change how the same per-face and per-cell arithmetic is
-    distributed: two coarse steps agree bit for bit under all 32
-    configurations."""
+    """Tile policy, z-chunk, persistent vs one-block-per-item launches, XCD
+    chunking and the update's z-chunk only change how the same per-face and
+    per-cell arithmetic is distributed: two coarse steps agree bit for bit
+    under all 32 configurations (each with one of the update z-chunks 1, 2,
+    3, 8, all four met under each launch mode)."""
     ndim, N0, L, grids, fields = _setup(key)
     ref = None
     for pol in (0, 1):
-        for zc in (8, 16, 32, 64):
+        for zi, zc in enumerate((8, 16, 32, 64)):
             for per in (0, 1, 2, 3):
-                log(f"case: launch config {key} policy={pol} zchunk={zc} mode={per}")
+                uz = (1, 2, 3, 8)[(zi + per) % 4]
+                log(f"case: launch config {key} policy={pol} zchunk={zc} mode={per} update zchunk={uz}")
                 H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
-                H.set_launch_config(pol, zc, per)
+                H.set_launch_config(pol, zc, per, uz)
                 assert A.amr_get_launch_config(H.h) == (pol, zc, per)
+                assert A.amr_get_update_zchunk(H.h) == uz
                 Ua, Ub = H.new_state(), H.new_state()
                 for gi, f in enumerate(fields):
                     H.load_primitive(Ua, gi, f["prim"], f["b"])
@@ -166,8 +169,9 @@ def test_every_launch_configuration_gives_identical_results(key):
 
 
 def test_autotune_keeps_the_state_and_the_results():
-    """The autotuner times all 32 configurations without changing what the
-    next coarse step computes."""
+    """The autotuner times all 32 launch configurations and then the update
+    z-chunks under the fastest, without changing what the next coarse step
+    computes."""
     import torch
     ndim, N0, L, grids, fields = _setup("3d")
     ref, _, _ = amr_gpu(ndim, N0, L, grids, fields, 2)
@@ -180,6 +184,9 @@ def test_autotune_keeps_the_state_and_the_results():
     log(f"autotune chose {table[chosen]}")
     assert 0 <= chosen < A.TUNE_CANDIDATES and all(t[3] > 0 for t in table)
     assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
+    assert A.amr_get_update_zchunk(H.h) == table[chosen][4]
+    assert [t[4] for t in table[32:]] == [1, 2, 4, 8]
+    assert all(tuple(t[:3]) == tuple(table[32][:3]) for t in table[32:])
     par = H.coarse_step(Ua, Ub, par, 0)
     torch.cuda.synchronize()
     got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
