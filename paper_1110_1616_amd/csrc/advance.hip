@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           // cell state U + du and B at time n; one writer per cell (the
           // tile's own cells, plus the grid's first column / row / plane)
           if (k >= item.z0 && (tx >= 1 || cx == cl) && (ty >= 1 || cy == cl)) {
-            const T ir = T(1) / (wcur[0] + du[0]);
+            const T ir = drcp(wcur[0] + du[0]);
             const T vx = (wcur[0] * wcur[1] + du[1]) * ir;
             const T vy = (wcur[0] * wcur[2] + du[2]) * ir;
             const T vz = (wcur[0] * wcur[3] + du[3]) * ir;

@@ -106,7 +106,7 @@ __device__ __forceinline__ bool predict_emit(const T (&w)[8], const T (&wxm)[8],
                                              const T (&wzp)[8], const T (&fb)[3][2], T hdt, const T (&idx)[3], T gam,
                                              Emit&& emit, T (&du_out)[8]) {
   const T gm1 = gam - T(1);
-  const T gm1_inv = T(1) / gm1;
+  const T gm1_inv = drcp(gm1);
   T sl[3][8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {

@@ -21,6 +21,50 @@ template <> __host__ __device__ __forceinline__ float dsqrt<float>(float x) { re
 
 template <class T> __host__ __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
 
+// Reciprocal of a nonzero finite normal x.  On the device: the hardware
+// estimate refined by Newton-Raphson steps r <- r + r (1 - x r) (two in
+// double, one in float), each error term formed with one fused multiply-add,
+// which leaves about one ulp (the correctly rounded division costs twice the
+// instructions); on the host, and for other types: plain division.
+__device__ __forceinline__ double drcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float drcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+__host__ __forceinline__ double drcp(double x) { return 1.0 / x; }
+__host__ __forceinline__ float drcp(float x) { return 1.0f / x; }
+template <class T> __host__ __device__ __forceinline__ T drcp(T x) { return T(1) / x; }
+
+// Square root of a non-negative finite x (0 for x <= 0).  On the device in
+// double: Goldschmidt's iteration from the hardware reciprocal square root
+// estimate y ~ 1/sqrt(x) (g = x y -> sqrt(x), h = y/2 -> 1/(2 sqrt(x)), one
+// coupled step, then two corrections g <- g + (x - g^2) h), without the
+// rescaling of subnormal inputs the general routine does; elsewhere the
+// library square root.
+__device__ __forceinline__ double psqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
+}
+__device__ __forceinline__ float psqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
+__host__ __forceinline__ double psqrt(double x) { return x > 0.0 ? __builtin_sqrt(x) : 0.0; }
+__host__ __forceinline__ float psqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
+template <class T> __host__ __device__ __forceinline__ T psqrt(T x) { return x > T(0) ? dsqrt(x) : T(0); }
+
 // minmod limiter: 0 when the one-sided differences disagree in sign (or one
 // is zero), else the one of smaller magnitude (a on ties).
 template <class T> __host__ __device__ __forceinline__ T limiter_minmod(T a, T b) {
@@ -44,7 +88,7 @@ template <class T> __host__ __device__ __forceinline__ void to_conserved(const T
 
 // U -> W for one state.
 template <class T> __host__ __device__ __forceinline__ void to_primitive(const T (&u)[8], T (&w)[8], T gm1) {
-  T ir = T(1) / u[0];
+  T ir = drcp(u[0]);
   w[0] = u[0];
   w[1] = u[1] * ir;
   w[2] = u[2] * ir;
@@ -82,12 +126,11 @@ __host__ __device__ __forceinline__ void flux_along(const T (&w)[8], T (&f)[8], 
 // Fast magnetosonic speed for density r, pressure p, |B|^2 = b2 and the field
 // component along the direction bn.
 template <class T> __host__ __device__ __forceinline__ T fast_magnetosonic(T r, T p, T b2, T bn, T gam) {
-  T ir = T(1) / r;
+  T ir = drcp(r);
   T gp = gam * p;
   T a = (gp + b2) * ir;
   T d = a * a - T(4) * gp * bn * bn * ir * ir;
-  d = d > T(0) ? d : T(0);
-  return dsqrt(T(0.5) * (a + dsqrt(d)));
+  return psqrt(T(0.5) * (a + psqrt(d)));
 }
 
 // HLLD flux (Miyoshi & Kusano 2005).  Inputs in the rotated frame:
@@ -98,7 +141,7 @@ template <class T> __host__ __device__ __forceinline__ T fast_magnetosonic(T r, 
 // S*_L >= 0, S_M >= 0, S*_R >= 0, S_R >= 0; else the right state).
 template <class T>
 __host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T (&qr)[8], T bn, T gam, T (&f)[7]) {
-  const T gm1_inv = T(1) / (gam - T(1));
+  const T gm1_inv = drcp(gam - T(1));
   const T bn2 = bn * bn;
 
   // Left / right totals.
@@ -120,7 +163,7 @@ __host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T 
   T dr = sr - qr[1];
   T rdl = ql[0] * dl;
   T rdr = qr[0] * dr;
-  T sm = (rdr * qr[1] - rdl * ql[1] - ptr + ptl) / (rdr - rdl);
+  T sm = (rdr * qr[1] - rdl * ql[1] - ptr + ptl) * drcp(rdr - rdl);
   T pts = ptl + rdl * (sm - ql[1]);
   const T tiny = T(1e-12) * pts;
 
@@ -129,11 +172,11 @@ __host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T 
   T rsr, vsr, wsr, bysr, bzsr, esr;
   {
     T dsm = sl - sm;
-    T idsm = T(1) / dsm;
+    T idsm = drcp(dsm);
     rsl = rdl * idsm;
     T den = rdl * dsm - bn2;
     bool deg = dabs(den) <= tiny;
-    T iden = deg ? T(0) : T(1) / den;
+    T iden = deg ? T(0) : drcp(den);
     T fv = bn * (sm - ql[1]) * iden;
     T fb = (rdl * dl - bn2) * iden;
     vsl = deg ? ql[2] : ql[2] - ql[6] * fv;
@@ -146,11 +189,11 @@ __host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T 
   }
   {
     T dsm = sr - sm;
-    T idsm = T(1) / dsm;
+    T idsm = drcp(dsm);
     rsr = rdr * idsm;
     T den = rdr * dsm - bn2;
     bool deg = dabs(den) <= tiny;
-    T iden = deg ? T(0) : T(1) / den;
+    T iden = deg ? T(0) : drcp(den);
     T fv = bn * (sm - qr[1]) * iden;
     T fb = (rdr * dr - bn2) * iden;
     vsr = deg ? qr[2] : qr[2] - qr[6] * fv;
@@ -163,14 +206,14 @@ __host__ __device__ __forceinline__ void riemann_hlld(const T (&ql)[8], const T 
   }
 
   // Alfven speeds and the inner (double-star) state.
-  T sql = dsqrt(rsl);
-  T sqr = dsqrt(rsr);
+  T sql = psqrt(rsl);
+  T sqr = psqrt(rsr);
   T abn = dabs(bn);
-  T ssl = sm - abn / sql;
-  T ssr = sm + abn / sqr;
+  T ssl = sm - abn * drcp(sql);
+  T ssr = sm + abn * drcp(sqr);
   bool ddeg = T(0.5) * bn2 <= tiny;
   T sg = bn > T(0) ? T(1) : T(-1);
-  T isum = T(1) / (sql + sqr);
+  T isum = drcp(sql + sqr);
   T vss = (sql * vsl + sqr * vsr + (bysr - bysl) * sg) * isum;
   T wss = (sql * wsl + sqr * wsr + (bzsr - bzsl) * sg) * isum;
   T byss = (sql * bysr + sqr * bysl + sql * sqr * (vsr - vsl) * sg) * isum;
