@@ -168,11 +168,14 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 #pragma unroll
     for (int q = 0; q < 7; ++q) zcarry[q] = T(0);
 
-    // prologue: W(kstart-1) own (3D), W(kstart) own + ring into LDS
+    // prologue: W(kstart-1) and W(kstart+1) own (3D), W(kstart) own + ring
+    // into LDS; in 3-D the own cell's loads then run two planes ahead (the
+    // predictor of plane k needs W(k+1))
     if (NDIM == 3 && ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart - 1), ix.sy, ix.sz, gm1, wprev);
 #pragma unroll
     for (int d = 0; d < 3; ++d) fbcur[d][0] = fbcur[d][1] = fbnext[d][0] = fbnext[d][1] = T(0);
     if (ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, kstart), ix.sy, ix.sz, gm1, wcur, fbcur);
+    if (NDIM == 3 && ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, kstart + 1), ix.sy, ix.sz, gm1, wnext, fbnext);
     if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, kstart), ix.sy, ix.sz, gm1, wring);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -182,9 +185,15 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     __syncthreads();
 
     for (int k = kstart; k < kend; ++k) {
+      // raw fields of the own cell two planes up and of the ring cell one
+      // plane up, converted once the predictor is done and before any flux
+      // store of this plane: the loads have the predictor to arrive in, and
+      // waiting for them does not wait for this plane's stores
+      T rnext[5], rfb[3][2], rring[5], rrfb[3][2];
+      const bool pf = NDIM == 3 && ook && k + 2 <= kend;
       if (NDIM == 3) {
-        if (ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, k + 1), ix.sy, ix.sz, gm1, wnext, fbnext);
-        if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, k + 1), ix.sy, ix.sz, gm1, wring);
+        if (pf) load_raw3<T>(U, ix(cx, cy, k + 2), ix.sy, ix.sz, rnext, rfb);
+        if (rok) load_raw3<T>(U, ix(rcx, rcy, k + 1), ix.sy, ix.sz, rring, rrfb);
       }
       Pred<T, NDIM> pr;
       if (act) {
@@ -227,37 +236,13 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
         }
       }
       __syncthreads();
-      if (own && k >= item.z0) {
-        const int64_t e = ix(cx, cy, k);
-        T f[7];
-        if (cx > cl) {
-          T l[7];
-#pragma unroll
-          for (int q = 0; q < 7; ++q) l[q] = sX[q][tid - 1];
-          hlld7(l, pr.m[0], fbcur[0][0], gam, f);
-#pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[0][q][e] = f[q];
-        }
-        if (cy > cl) {
-          T l[7];
-#pragma unroll
-          for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - tw];
-          hlld7(l, pr.m[1], fbcur[1][0], gam, f);
-#pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
-        }
-        if (NDIM == 3 && k > cl) {
-          hlld7(zcarry, pr.m[2], fbcur[2][0], gam, f);
-#pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[2][q][e] = f[q];
-        }
-      }
+      // every read of this plane's W is done: the next plane's W (own cell
+      // and ring) goes into LDS while the Riemann problems run, and the
+      // own-cell planes move up by one (the Riemann problems read only the
+      // low-face normal fields bn of this plane)
+      T bn[3] = {fbcur[0][0], fbcur[1][0], fbcur[2][0]};
       if (NDIM == 3) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) zcarry[q] = pr.p[2][q];
-      }
-      __syncthreads();
-      if (NDIM == 3) {
+        if (rok) raw3_to_prim<T>(rring, rrfb, gm1, wring);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (live) sW[q][eo] = wnext[q];
@@ -270,8 +255,45 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           fbcur[d][0] = fbnext[d][0];
           fbcur[d][1] = fbnext[d][1];
         }
-        __syncthreads();
+        if (pf) {
+          raw3_to_prim<T>(rnext, rfb, gm1, wnext);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            fbnext[d][0] = rfb[d][0];
+            fbnext[d][1] = rfb[d][1];
+          }
+        }
       }
+      if (own && k >= item.z0) {
+        const int64_t e = ix(cx, cy, k);
+        T f[7];
+        if (cx > cl) {
+          T l[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) l[q] = sX[q][tid - 1];
+          hlld7(l, pr.m[0], bn[0], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[0][q][e] = f[q];
+        }
+        if (cy > cl) {
+          T l[7];
+#pragma unroll
+          for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - tw];
+          hlld7(l, pr.m[1], bn[1], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
+        }
+        if (NDIM == 3 && k > cl) {
+          hlld7(zcarry, pr.m[2], bn[2], gam, f);
+#pragma unroll
+          for (int q = 0; q < 7; ++q) F.f[2][q][e] = f[q];
+        }
+      }
+      if (NDIM == 3) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) zcarry[q] = pr.p[2][q];
+      }
+      __syncthreads();
     }
   }
   retire<PERSIST>(q);

@@ -68,6 +68,36 @@ __device__ __forceinline__ void load_prim_faces(const DevState<T>& U, int64_t e,
   to_primitive(u, w, gm1);
 }
 
+// load_prim_faces in two halves, so the loads can be issued a plane ahead
+// of the arithmetic: the raw conserved fields and face fields of cell e
+// (3-D), then the same conversion load_prim_faces does.
+template <class T>
+__device__ __forceinline__ void load_raw3(const DevState<T>& U, int64_t e, int32_t sy, int32_t sz, T (&u)[5],
+                                          T (&fb)[3][2]) {
+  u[0] = U.f[0][e];
+  u[1] = U.f[1][e];
+  u[2] = U.f[2][e];
+  u[3] = U.f[3][e];
+  u[4] = U.f[4][e];
+  fb[0][0] = U.f[5][e];
+  fb[0][1] = U.f[5][e + 1];
+  fb[1][0] = U.f[6][e];
+  fb[1][1] = U.f[6][e + sy];
+  fb[2][0] = U.f[7][e];
+  fb[2][1] = U.f[7][e + sz];
+}
+
+template <class T>
+__device__ __forceinline__ void raw3_to_prim(const T (&r)[5], const T (&fb)[3][2], T gm1, T (&w)[8]) {
+  T u[8];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = r[q];
+  u[5] = T(0.5) * (fb[0][0] + fb[0][1]);
+  u[6] = T(0.5) * (fb[1][0] + fb[1][1]);
+  u[7] = T(0.5) * (fb[2][0] + fb[2][1]);
+  to_primitive(u, w, gm1);
+}
+
 __device__ __forceinline__ void flag_bad(ErrBlock* err, int64_t e) {
   unsigned old = atomicOr(&err->flags, 1u);
   if ((old & 1u) == 0u) atomicExch((unsigned long long*)&err->first_bad, (unsigned long long)e);
