@@ -113,8 +113,10 @@ typedef struct amr_hierarchy amr_hierarchy;
  * level-(l-1) interiors, periodic images included).  Builds the device
  * tables: grid descriptors, ghost fill maps (same-level copy before
  * prolongation), synchronisation registers and the finest-level-first work
- * lists of every launch cycle.  On failure *out is NULL and the status says
- * why (amr_last_error() has the text). */
+ * lists of every launch cycle.  Limits (AMR_EUNSUPPORTED beyond them): under
+ * 2^31 elements per pool and under 4 GiB per field array (the flux kernel
+ * addresses by 32-bit byte offsets).  On failure *out is NULL and the status
+ * says why (amr_last_error() has the text). */
 amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids, amr_hierarchy** out);
 
 /* Run every check and table build of amr_create() on the host only (no

@@ -125,7 +125,8 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     const GridDesc G = grids[item.grid];
     // each level's current data lives in S0 or S1 (bit `level` of parity)
     const DevState<T> U = ((parity >> G.level) & 1u) ? S1 : S0;
-    const Idx<NDIM> ix(G);
+    const Idx<NDIM> ix(G);  // element index, for error reports only
+    const IdxB<NDIM, T> bx(G);
     const int gv = item.gv;
     const int cl = -gv + 1;
     const int chx = G.n[0] + gv - 1, chy = G.n[1] + gv - 1;
@@ -171,12 +172,12 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
     // prologue: W(kstart-1) and W(kstart+1) own (3D), W(kstart) own + ring
     // into LDS; in 3-D the own cell's loads then run two planes ahead (the
     // predictor of plane k needs W(k+1))
-    if (NDIM == 3 && ook) load_prim<T, NDIM>(U, ix(cx, cy, kstart - 1), ix.sy, ix.sz, gm1, wprev);
+    if (NDIM == 3 && ook) load_prim_b<T, NDIM>(U, bx(cx, cy, kstart - 1), bx.sy, bx.sz, gm1, wprev);
 #pragma unroll
     for (int d = 0; d < 3; ++d) fbcur[d][0] = fbcur[d][1] = fbnext[d][0] = fbnext[d][1] = T(0);
-    if (ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, kstart), ix.sy, ix.sz, gm1, wcur, fbcur);
-    if (NDIM == 3 && ook) load_prim_faces<T, NDIM>(U, ix(cx, cy, kstart + 1), ix.sy, ix.sz, gm1, wnext, fbnext);
-    if (rok) load_prim<T, NDIM>(U, ix(rcx, rcy, kstart), ix.sy, ix.sz, gm1, wring);
+    if (ook) load_prim_faces_b<T, NDIM>(U, bx(cx, cy, kstart), bx.sy, bx.sz, gm1, wcur, fbcur);
+    if (NDIM == 3 && ook) load_prim_faces_b<T, NDIM>(U, bx(cx, cy, kstart + 1), bx.sy, bx.sz, gm1, wnext, fbnext);
+    if (rok) load_prim_b<T, NDIM>(U, bx(rcx, rcy, kstart), bx.sy, bx.sz, gm1, wring);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (live) sW[q][eo] = wcur[q];
@@ -192,8 +193,8 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
       T rnext[5], rfb[3][2], rring[5], rrfb[3][2];
       const bool pf = NDIM == 3 && ook && k + 2 <= kend;
       if (NDIM == 3) {
-        if (pf) load_raw3<T>(U, ix(cx, cy, k + 2), ix.sy, ix.sz, rnext, rfb);
-        if (rok) load_raw3<T>(U, ix(rcx, rcy, k + 1), ix.sy, ix.sz, rring, rrfb);
+        if (pf) load_raw3<T>(U, bx(cx, cy, k + 2), bx.sy, bx.sz, rnext, rfb);
+        if (rok) load_raw3<T>(U, bx(rcx, rcy, k + 1), bx.sy, bx.sz, rring, rrfb);
       }
       Pred<T, NDIM> pr;
       if (act) {
@@ -206,7 +207,6 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           wyp[q] = sW[q][eo + kW];
         }
         if ((wcur[0] <= T(0)) || (wcur[4] <= T(0))) flag_bad(err, ix(cx, cy, k));
-        const int64_t e = ix(cx, cy, k);
         bool ok;
         if constexpr (UPWIND) {
           T du[8];
@@ -219,16 +219,17 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
             const T vx = (wcur[0] * wcur[1] + du[1]) * ir;
             const T vy = (wcur[0] * wcur[2] + du[2]) * ir;
             const T vz = (wcur[0] * wcur[3] + du[3]) * ir;
+            const auto eb = bx(cx, cy, k);
             if (NDIM == 3) {
-              F.e[0][e] = vz * wcur[6] - vy * wcur[7];
-              F.e[1][e] = vx * wcur[7] - vz * wcur[5];
+              stb(F.e[0], eb, vz * wcur[6] - vy * wcur[7]);
+              stb(F.e[1], eb, vx * wcur[7] - vz * wcur[5]);
             }
-            F.e[2][e] = vy * wcur[5] - vx * wcur[6];
+            stb(F.e[2], eb, vy * wcur[5] - vx * wcur[6]);
           }
         } else {
           ok = predict<T, NDIM>(wcur, wxm, wxp, wym, wyp, wprev, wnext, fbcur, hdt, idx, gam, pr);
         }
-        if (!ok) flag_bad(err, e);
+        if (!ok) flag_bad(err, ix(cx, cy, k));
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
           sX[q][tid] = pr.p[0][q];
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
         }
       }
       if (own && k >= item.z0) {
-        const int64_t e = ix(cx, cy, k);
+        const auto eb = bx(cx, cy, k);
         T f[7];
         if (cx > cl) {
           T l[7];
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           for (int q = 0; q < 7; ++q) l[q] = sX[q][tid - 1];
           hlld7(l, pr.m[0], bn[0], gam, f);
 #pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[0][q][e] = f[q];
+          for (int q = 0; q < 7; ++q) stb(F.f[0][q], eb, f[q]);
         }
         if (cy > cl) {
           T l[7];
@@ -281,12 +282,12 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
           for (int q = 0; q < 7; ++q) l[q] = sY[q][tid - tw];
           hlld7(l, pr.m[1], bn[1], gam, f);
 #pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[1][q][e] = f[q];
+          for (int q = 0; q < 7; ++q) stb(F.f[1][q], eb, f[q]);
         }
         if (NDIM == 3 && k > cl) {
           hlld7(zcarry, pr.m[2], bn[2], gam, f);
 #pragma unroll
-          for (int q = 0; q < 7; ++q) F.f[2][q][e] = f[q];
+          for (int q = 0; q < 7; ++q) stb(F.f[2][q], eb, f[q]);
         }
       }
       if (NDIM == 3) {
@@ -408,15 +409,15 @@ __global__ __launch_bounds__(256) void k_emf(const GridDesc* __restrict__ grids,
   const int ehx = G.n[0] + item.gv - 1, ehy = G.n[1] + item.gv - 1;  // last edge index (inclusive)
   const int cx = item.x0 + tx, cy = item.y0 + ty;
   if (cx > ehx || cy > ehy) return;
-  const Idx<NDIM> ix(G);
-  const int64_t st[3] = {1, ix.sy, NDIM == 3 ? ix.sz : 0};
+  const IdxB<NDIM, T> bx(G);
+  const int32_t sb[3] = {(int32_t)sizeof(T), bx.sy, NDIM == 3 ? bx.sz : 0};
   for (int k = item.z0; k < item.z1; ++k) {
-    const int64_t e = ix(cx, cy, k);
+    const auto e = bx(cx, cy, k);
     if (NDIM == 3) {
-      F.edge[0][e] = edge_emf_upwind<0>(F, e, st);
-      F.edge[1][e] = edge_emf_upwind<1>(F, e, st);
+      stb(F.edge[0], e, edge_emf_upwind_b<0>(F, e, sb));
+      stb(F.edge[1], e, edge_emf_upwind_b<1>(F, e, sb));
     }
-    F.edge[2][e] = edge_emf_upwind<2>(F, e, st);
+    stb(F.edge[2], e, edge_emf_upwind_b<2>(F, e, sb));
   }
 }
 

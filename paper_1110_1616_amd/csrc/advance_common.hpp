@@ -19,6 +19,67 @@ template <int NDIM> struct Idx {
   }
 };
 
+// Addressing by 32-bit byte offsets from the start of the level arrays (a
+// field's array holds under 2^32 bytes; the hierarchy's set-up checks): the
+// array pointers stay in scalar registers and each lane carries one 32-bit
+// offset, so loads and stores take the scalar-base form instead of 64-bit
+// lane addresses.  IdxB gives the byte offset of interior cell (i, j, k) of a
+// grid (i, j, k >= -g); the sums wrap modulo 2^32 to the exact offset.
+template <int NDIM, class T> struct IdxB {
+  using B = typename ByteOffset<T>::type;
+  B b0;            // cell (0,0,0)
+  int32_t sy, sz;  // row and plane strides
+  __device__ __forceinline__ IdxB(const GridDesc& G) {
+    sy = G.P[0] * (int32_t)sizeof(T);
+    sz = G.P[0] * G.P[1] * (int32_t)sizeof(T);
+    const int64_t e0 = G.off + G.g + (int64_t)G.g * G.P[0] + (NDIM == 3 ? (int64_t)G.g * G.P[0] * G.P[1] : 0);
+    b0 = (B)(e0 * (int64_t)sizeof(T));
+  }
+  __device__ __forceinline__ B operator()(int i, int j, int k) const {
+    return b0 + (B)(i * (int32_t)sizeof(T) + j * sy + (NDIM == 3 ? k * sz : 0));
+  }
+};
+
+// load_prim / load_prim_faces at byte offset b (strides sy, sz in bytes).
+template <class T, int NDIM, class B>
+__device__ __forceinline__ void load_prim_b(const DevState<T>& U, B b, int32_t sy, int32_t sz, T gm1,
+                                            T (&w)[8]) {
+  T u[8];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = ldb(U.f[q], b);
+  u[5] = T(0.5) * (ldb(U.f[5], b) + ldb(U.f[5], b, (int)sizeof(T)));
+  u[6] = T(0.5) * (ldb(U.f[6], b) + ldb(U.f[6], b + sy));
+  if (NDIM == 3)
+    u[7] = T(0.5) * (ldb(U.f[7], b) + ldb(U.f[7], b + sz));
+  else
+    u[7] = ldb(U.f[7], b);
+  to_primitive(u, w, gm1);
+}
+
+template <class T, int NDIM, class B>
+__device__ __forceinline__ void load_prim_faces_b(const DevState<T>& U, B b, int32_t sy, int32_t sz, T gm1,
+                                                  T (&w)[8], T (&fb)[3][2]) {
+  T u[8];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = ldb(U.f[q], b);
+  fb[0][0] = ldb(U.f[5], b);
+  fb[0][1] = ldb(U.f[5], b, (int)sizeof(T));
+  fb[1][0] = ldb(U.f[6], b);
+  fb[1][1] = ldb(U.f[6], b + sy);
+  u[5] = T(0.5) * (fb[0][0] + fb[0][1]);
+  u[6] = T(0.5) * (fb[1][0] + fb[1][1]);
+  if (NDIM == 3) {
+    fb[2][0] = ldb(U.f[7], b);
+    fb[2][1] = ldb(U.f[7], b + sz);
+    u[7] = T(0.5) * (fb[2][0] + fb[2][1]);
+  } else {
+    fb[2][0] = T(0);
+    fb[2][1] = T(0);
+    u[7] = ldb(U.f[7], b);
+  }
+  to_primitive(u, w, gm1);
+}
+
 // Primitive state of cell e (element index) from the conserved state and
 // the bounding faces.
 template <class T, int NDIM>
@@ -68,23 +129,20 @@ __device__ __forceinline__ void load_prim_faces(const DevState<T>& U, int64_t e,
   to_primitive(u, w, gm1);
 }
 
-// load_prim_faces in two halves, so the loads can be issued a plane ahead
-// of the arithmetic: the raw conserved fields and face fields of cell e
-// (3-D), then the same conversion load_prim_faces does.
-template <class T>
-__device__ __forceinline__ void load_raw3(const DevState<T>& U, int64_t e, int32_t sy, int32_t sz, T (&u)[5],
+// load_prim_faces_b in two halves, so the loads can be issued a plane ahead
+// of the arithmetic: the raw conserved fields and face fields of the cell at
+// byte offset b (3-D), then the same conversion.
+template <class T, class B>
+__device__ __forceinline__ void load_raw3(const DevState<T>& U, B b, int32_t sy, int32_t sz, T (&u)[5],
                                           T (&fb)[3][2]) {
-  u[0] = U.f[0][e];
-  u[1] = U.f[1][e];
-  u[2] = U.f[2][e];
-  u[3] = U.f[3][e];
-  u[4] = U.f[4][e];
-  fb[0][0] = U.f[5][e];
-  fb[0][1] = U.f[5][e + 1];
-  fb[1][0] = U.f[6][e];
-  fb[1][1] = U.f[6][e + sy];
-  fb[2][0] = U.f[7][e];
-  fb[2][1] = U.f[7][e + sz];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) u[q] = ldb(U.f[q], b);
+  fb[0][0] = ldb(U.f[5], b);
+  fb[0][1] = ldb(U.f[5], b, (int)sizeof(T));
+  fb[1][0] = ldb(U.f[6], b);
+  fb[1][1] = ldb(U.f[6], b + sy);
+  fb[2][0] = ldb(U.f[7], b);
+  fb[2][1] = ldb(U.f[7], b + sz);
 }
 
 template <class T>

@@ -70,6 +70,24 @@ template <class T> struct DevFlux {
   T* edge[3];
 };
 
+// Element load / store at a 32-bit byte offset b from a base pointer that is
+// uniform over the work item: the scalar-base address form, one 32-bit lane
+// register per access instead of a 64-bit address.
+// The offset type: 32-bit for the arithmetic types; the frozen-branch pair
+// types (finite-difference verification only) specialise it to 64-bit.
+template <class T> struct ByteOffset { using type = uint32_t; };
+
+template <class T, class B> __device__ __forceinline__ T ldb(const T* p, B b) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + b);
+}
+// (the element `imm` bytes further on, folded into the instruction)
+template <class T, class B> __device__ __forceinline__ T ldb(const T* p, B b, int imm) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + b + imm);
+}
+template <class T, class B> __device__ __forceinline__ void stb(T* p, B b, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + b) = v;
+}
+
 // Error flag block in device memory: word 0 = flags, word 1..2 = first bad
 // element (int64), words 4.. = reduction scratch.
 struct ErrBlock {

@@ -48,6 +48,23 @@ __device__ __forceinline__ T emf_at(const DevFlux<T>& F, int64_t e, const int64_
   else return edge_emf<A>(F, e, st);
 }
 
+// edge_emf_upwind at byte offset b (byte strides sb): identical arithmetic,
+// so identical values.
+template <int A, class T, class Off>
+__device__ __forceinline__ T edge_emf_upwind_b(const DevFlux<T>& F, Off b, const int32_t (&sb)[3]) {
+  constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
+  const T bS = -ldb(F.f[B][5], b - sb[C]), bN = -ldb(F.f[B][5], b);
+  const T cW = ldb(F.f[C][6], b - sb[B]), cE = ldb(F.f[C][6], b);
+  const T eSW = ldb(F.e[A], b - sb[B] - sb[C]), eSE = ldb(F.e[A], b - sb[C]);
+  const T eNW = ldb(F.e[A], b - sb[B]), eNE = ldb(F.e[A], b);
+  auto upw = [](T flux, T lo, T hi) { return flux > T(0) ? lo : (flux < T(0) ? hi : T(0.5) * (lo + hi)); };
+  const T dc_hi = upw(ldb(F.f[B][0], b), eNW - cW, eNE - cE);
+  const T dc_lo = upw(ldb(F.f[B][0], b - sb[C]), cW - eSW, cE - eSE);
+  const T db_hi = upw(ldb(F.f[C][0], b), eSE - bS, eNE - bN);
+  const T db_lo = upw(ldb(F.f[C][0], b - sb[B]), bS - eSW, bN - eNW);
+  return T(0.25) * ((bS + bN) + (cW + cE)) + T(0.25) * ((dc_lo - dc_hi) + (db_lo - db_hi));
+}
+
 // Rotated flux component of direction d that carries lab conserved slot s
 // (0 rho, 1..3 momentum, 4 energy, 7 the cell-centred Bz of 2D).
 __device__ __forceinline__ int flux_comp(int s, int d) {

@@ -7,6 +7,7 @@
 // member is then a difference of one smooth branch of the discrete map, the
 // map whose exact derivative the adjoint computes.
 #pragma once
+#include "amr_internal.hpp"
 #include "mhd_device.hpp"
 
 namespace amr {
@@ -37,6 +38,9 @@ template <> __host__ __device__ __forceinline__ Frozen<double> dsqrt<Frozen<doub
 template <> __host__ __device__ __forceinline__ Frozen<float> dsqrt<Frozen<float>>(Frozen<float> x) {
   return Frozen<float>(__builtin_sqrtf(x.b), __builtin_sqrtf(x.p), 0);
 }
+
+// 64-bit byte offsets for the pair types in the advance kernels' addressing
+template <class S> struct ByteOffset<Frozen<S>> { using type = uint64_t; };
 
 using FrozenD = Frozen<double>;
 using FrozenF = Frozen<float>;

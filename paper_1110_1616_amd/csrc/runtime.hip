@@ -1421,6 +1421,8 @@ amr_hierarchy* build_hierarchy(const amr_params* p, const amr_grid* grids, int32
     }
     h->total_elems = off;
     if (off >= ((int64_t)1 << 31)) throw Error(AMR_EUNSUPPORTED, "hierarchy exceeds 2^31 elements per pool");
+    // the advance kernels address the level arrays by 32-bit byte offsets
+    if (off * h->esize >= ((int64_t)1 << 32)) throw Error(AMR_EUNSUPPORTED, "hierarchy exceeds 4 GiB per field");
     h->upwind_emf = p->emf == AMR_EMF_UPWIND;
     h->flux_bytes = (h->upwind_emf ? 27 : 21) * off * (int64_t)h->esize;
     h->reg_offset = (h->flux_bytes + 255) / 256 * 256;
