@@ -109,3 +109,12 @@ def test_pointwise_adjoints_pass_the_dot_product_test(which):
     err = L.amr_selfcheck_adjoint(which, 300, 1234 + which)
     assert 0.0 <= err <= 1e-9, err
     assert L.amr_selfcheck_adjoint(7, 10, 1) == -1.0
+
+
+def test_validate_refuses_fields_over_4gib():
+    """The flux kernel addresses a field's array by 32-bit byte offsets, so a
+    hierarchy whose FP64 field arrays exceed 4 GiB is refused up front."""
+    n = 816  # padded (816 + 2*4 + 1)^3 elements * 8 B > 4 GiB, under 2^31 elements
+    p = A.make_params(3, (n, n, n), nlevels=1, ghost=4)
+    with pytest.raises(A.AmrError, match="4 GiB"):
+        A.amr_validate(p, A.make_grids([(0, (0, 0, 0), (n, n, n))]))
