@@ -159,6 +159,7 @@ def amr_workload(args, deep=False):
         N0 = (args.n0_deep,) * 3
         L = 6
         grids, fields = I.deep_hierarchy(args.n0_deep, seed=5)
+        progress(f"deep hierarchy generated: {len(grids)} grids")
     else:
         N0 = (args.n0,) * 3
         L = 3
@@ -166,8 +167,11 @@ def amr_workload(args, deep=False):
         fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
     H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4, dtype=args.dtype, emf=EMF[args.emf])
     Ua, Ub = H.new_state(), H.new_state()
+    progress("hierarchy created; loading the initial state")
     for gi, f in enumerate(fields):
         H.load_primitive(Ua, gi, f["prim"], f["b"])
+        if gi % 1000 == 999:
+            progress(f"loaded {gi + 1} grids")
     cells = [0] * L
     for (l, lo, hi) in grids:
         cells[l] += int(np.prod([hi[a] - lo[a] for a in range(3)]))
@@ -297,6 +301,14 @@ def single_workload(args):
 
 EMF = {"mean": 0, "upwind": 1}
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """Phase line on stderr (stdout carries only the JSON result line)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 WORKLOADS = {"amr3": amr_workload, "single128": single_workload, "deep6": lambda a: amr_workload(a, deep=True)}
 
 
@@ -405,8 +417,10 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_measure(reps=max(1, args.steps))}), flush=True)
         return
+    progress(f"building workload {args.workload}")
     W = WORKLOADS[args.workload](args)
     H, info = W["H"], W["info"]
+    progress(f"workload ready: {info['grids']} grids")
 
     def timed(fn, k):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -434,6 +448,7 @@ def main():
         tuned = {"chosen": {"tile_policy": pol, "zchunk": zc, "launch_mode": per,
                             "update_zchunk": A.amr_get_update_zchunk(H.h)}, "set_by": "--launch-config"}
     elif W.get("tune") and not args.no_autotune:
+        progress("autotuning the launch configuration")
         chosen, table = W["tune"]()
         torch.cuda.synchronize()
         tuned = {"chosen": {"tile_policy": table[chosen][0], "zchunk": table[chosen][1],
@@ -443,6 +458,7 @@ def main():
             W["eager"]()
         torch.cuda.synchronize()
     sched = None
+    progress("warm-up and launch configuration done")
     if W.get("schedules"):
         # launch-cycle schedule: window start (0) or the predictive eta
         # balance (1); both compute the same bits, the faster one is timed
@@ -465,6 +481,7 @@ def main():
             W["step"]()
 
     # timed region: K steps of the production path
+    progress(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     gpu_ms = timed(W["step"], args.steps)
     wall = time.perf_counter() - t0
@@ -478,6 +495,7 @@ def main():
 
     per_grid = None
     if W["per_grid"] is not None and args.per_grid_steps > 0:
+        progress("timing the per-grid path")
         pg_ms = timed(W["per_grid"], args.per_grid_steps)
         per_grid = float(info["cells"]) * args.per_grid_steps / (pg_ms / 1e3)
 
@@ -526,10 +544,13 @@ def main():
     if sched is not None:
         out["schedule"] = sched
     if W.get("regrid") and not args.no_regrid:
+        progress("measuring a regrid")
         out["regrid"] = W["regrid"]()
     if not args.no_adjoint:
+        progress("measuring the adjoint")
         out["adjoint"] = adjoint_measure()
     if not args.no_cpu_baseline:
+        progress("timing the CPU oracle sample")
         cs = W["cpu_sample"]()
         out["cpu_baseline"] = {"value": cs["updates"] / cs["seconds"], "unit": "cell-updates/s",
                                "cores": cs["threads"], "kind": "oracle", "sample": cs["sample"],
