@@ -1281,6 +1281,9 @@ void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws
 
 template <class T>
 void do_sync(amr_hierarchy* h, int f, const amr_state* Uf, amr_state* Uc, void* ws, hipStream_t s) {
+  // the synchronisation kernels are unrolled over ratio 2, the only one a
+  // multi-level hierarchy accepts
+  if (h->R != 2) throw Error(AMR_EUNSUPPORTED, "synchronisation needs refinement ratio 2");
   const SyncTables& t = h->sync[f];
   const T* freg = (const T*)((char*)ws + t.reg_off);
   const T* ereg =

@@ -17,20 +17,36 @@ inline int blocks_for(int64_t n) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// The refinement ratio of a synchronised hierarchy (the runtime refuses any
+// other): the gathers below are unrolled over it, so each thread issues all
+// of its loads before the first use and sums them in the order the
+// definition states (one memory latency per thread instead of one per term).
+constexpr int kR = 2;
+
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_reg_faces(const FaceRegEntry* __restrict__ ent, int n, DevFlux<T> F,
                                                    T* __restrict__ reg, int nreg, int slot,
                                                    const double* __restrict__ dt0p, double dt_div) {
   const T dt = T(dt0p[0] / dt_div);
-  const int ns = NDIM == 2 ? 6 : 5;
+  constexpr int ns = NDIM == 2 ? 6 : 5;
+  constexpr int nmax = NDIM == 3 ? kR * kR : kR;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const FaceRegEntry e = ent[t];
     T* out = reg + ((int64_t)slot * nreg + e.reg) * 6;
+    T v[ns][nmax];
+#pragma unroll
     for (int q = 0; q < ns; ++q) {
       const int s = q < 5 ? q : 7;
       const T* f = F.f[e.d][flux_comp(s, e.d)];
+#pragma unroll
+      for (int i = 0; i < nmax; ++i) v[q][i] = i < e.n ? f[e.e[i]] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < ns; ++q) {
       T m = T(0);
-      for (int i = 0; i < e.n; ++i) m += f[e.e[i]];
+#pragma unroll
+      for (int i = 0; i < nmax; ++i)
+        if (i < e.n) m += v[q][i];
       out[q] = dt * (m / T(e.n));
     }
   }
@@ -46,34 +62,57 @@ __global__ __launch_bounds__(256) void k_reg_edges(const EdgeRegEntry* __restric
     const EdgeRegEntry e = ent[t];
     const GridDesc G = grids[e.grid];
     const int64_t st[3] = {1, G.P[0], NDIM == 3 ? (int64_t)G.P[0] * G.P[1] : 0};
-    T m = T(0);
-    for (int i = 0; i < e.n; ++i) {
-      T v;
-      if (e.a == 0) v = emf_at<0, UPWIND>(F, e.e[i], st);
-      else if (e.a == 1) v = emf_at<1, UPWIND>(F, e.e[i], st);
-      else v = emf_at<2, UPWIND>(F, e.e[i], st);
-      m += v;
+    T v[kR];
+#pragma unroll
+    for (int i = 0; i < kR; ++i) {
+      v[i] = T(0);
+      if (i < e.n) {
+        if (e.a == 0) v[i] = emf_at<0, UPWIND>(F, e.e[i], st);
+        else if (e.a == 1) v[i] = emf_at<1, UPWIND>(F, e.e[i], st);
+        else v[i] = emf_at<2, UPWIND>(F, e.e[i], st);
+      }
     }
+    T m = T(0);
+#pragma unroll
+    for (int i = 0; i < kR; ++i)
+      if (i < e.n) m += v[i];
     reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
   }
 }
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_reflux(const RefluxEntry* __restrict__ ent, int n, const T* __restrict__ reg,
-                                                int nreg, int R, DevState<T> U) {
-  const int ns = NDIM == 2 ? 6 : 5;
+                                                int nreg, DevState<T> U) {
+  constexpr int ns = NDIM == 2 ? 6 : 5;
+  constexpr int imax = 6;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const RefluxEntry e = ent[t];
+#pragma unroll
     for (int q = 0; q < ns; ++q) {
       const int s = q < 5 ? q : 7;
       T acc = U.f[s][e.cell];
-      for (int i = 0; i < e.n; ++i) {
-        const T* r = reg + (int64_t)e.reg[i] * 6 + q;
-        T fine = T(0);
-        for (int k = 1; k <= R; ++k) fine += r[(int64_t)k * nreg * 6];
-        const T delta = r[0] - fine;
-        acc += T(e.coef[i]) * delta;
+      T rc[imax], rf[imax][kR];
+#pragma unroll
+      for (int i = 0; i < imax; ++i) {
+        rc[i] = T(0);
+#pragma unroll
+        for (int k = 0; k < kR; ++k) rf[i][k] = T(0);
+        if (i < e.n) {
+          const T* r = reg + (int64_t)e.reg[i] * 6 + q;
+          rc[i] = r[0];
+#pragma unroll
+          for (int k = 0; k < kR; ++k) rf[i][k] = r[(int64_t)(k + 1) * nreg * 6];
+        }
       }
+#pragma unroll
+      for (int i = 0; i < imax; ++i)
+        if (i < e.n) {
+          T fine = T(0);
+#pragma unroll
+          for (int k = 0; k < kR; ++k) fine += rf[i][k];
+          const T delta = rc[i] - fine;
+          acc += T(e.coef[i]) * delta;
+        }
       U.f[s][e.cell] = acc;
     }
   }
@@ -81,46 +120,83 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxEntry* __restrict__ 
 
 template <class T>
 __global__ __launch_bounds__(256) void k_emffix(const EmfFixEntry* __restrict__ ent, int n, const T* __restrict__ reg,
-                                                int nreg, int R, DevState<T> U) {
+                                                int nreg, DevState<T> U) {
+  constexpr int imax = 4;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const EmfFixEntry e = ent[t];
-    T corr = T(0);
-    for (int i = 0; i < e.n; ++i) {
-      const T* r = reg + e.reg[i];
-      T fine = T(0);
-      for (int k = 1; k <= R; ++k) fine += r[(int64_t)k * nreg];
-      corr += T(e.coef[i]) * (fine - r[0]);
+    T rc[imax], rf[imax][kR];
+#pragma unroll
+    for (int i = 0; i < imax; ++i) {
+      rc[i] = T(0);
+#pragma unroll
+      for (int k = 0; k < kR; ++k) rf[i][k] = T(0);
+      if (i < e.n) {
+        const T* r = reg + e.reg[i];
+        rc[i] = r[0];
+#pragma unroll
+        for (int k = 0; k < kR; ++k) rf[i][k] = r[(int64_t)(k + 1) * nreg];
+      }
     }
+    T corr = T(0);
+#pragma unroll
+    for (int i = 0; i < imax; ++i)
+      if (i < e.n) {
+        T fine = T(0);
+#pragma unroll
+        for (int k = 0; k < kR; ++k) fine += rf[i][k];
+        corr += T(e.coef[i]) * (fine - rc[i]);
+      }
     U.f[5 + e.d][e.face] -= corr;
   }
 }
 
 template <class T, int NDIM>
 __global__ __launch_bounds__(256) void k_restrict(const RestrictEntry* __restrict__ ent, int n,
-                                                  const GridDesc* __restrict__ grids, int R, DevState<T> Uf,
+                                                  const GridDesc* __restrict__ grids, DevState<T> Uf,
                                                   DevState<T> Uc) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const RestrictEntry e = ent[t];
     const GridDesc G = grids[e.fgrid];
     const int64_t st[3] = {1, G.P[0], (int64_t)G.P[0] * G.P[1]};
     if (e.d < 0) {
-      const int ns = NDIM == 2 ? 6 : 5;
-      const int nz = NDIM == 3 ? R : 1;
+      constexpr int ns = NDIM == 2 ? 6 : 5;
+      constexpr int nz = NDIM == 3 ? kR : 1;
+      T v[ns][nz * kR * kR];
+#pragma unroll
+      for (int q = 0; q < ns; ++q) {
+        const int s = q < 5 ? q : 7;
+#pragma unroll
+        for (int kz = 0; kz < nz; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < kR; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < kR; ++kx)
+              v[q][(kz * kR + ky) * kR + kx] = Uf.f[s][e.src + kx + ky * st[1] + kz * st[2]];
+      }
+#pragma unroll
       for (int q = 0; q < ns; ++q) {
         const int s = q < 5 ? q : 7;
         T m = T(0);
-        for (int kz = 0; kz < nz; ++kz)
-          for (int ky = 0; ky < R; ++ky)
-            for (int kx = 0; kx < R; ++kx) m += Uf.f[s][e.src + kx + ky * st[1] + kz * st[2]];
-        Uc.f[s][e.dst] = m / T(R * R * nz);
+#pragma unroll
+        for (int c = 0; c < nz * kR * kR; ++c) m += v[q][c];
+        Uc.f[s][e.dst] = m / T(kR * kR * nz);
       }
     } else {
       const int d = e.d;
       const int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
-      const int n1 = a1 < NDIM ? R : 1, n2 = a2 < NDIM ? R : 1;
+      const int n1 = a1 < NDIM ? kR : 1, n2 = a2 < NDIM ? kR : 1;
+      T v[kR * kR];
+#pragma unroll
+      for (int i1 = 0; i1 < kR; ++i1)
+#pragma unroll
+        for (int i2 = 0; i2 < kR; ++i2)
+          v[i1 * kR + i2] = (i1 < n1 && i2 < n2) ? Uf.f[5 + d][e.src + i1 * st[a1] + i2 * st[a2]] : T(0);
       T m = T(0);
-      for (int i1 = 0; i1 < n1; ++i1)
-        for (int i2 = 0; i2 < n2; ++i2) m += Uf.f[5 + d][e.src + i1 * st[a1] + i2 * st[a2]];
+#pragma unroll
+      for (int i1 = 0; i1 < kR; ++i1)
+#pragma unroll
+        for (int i2 = 0; i2 < kR; ++i2)
+          if (i1 < n1 && i2 < n2) m += v[i1 * kR + i2];
       Uc.f[5 + d][e.dst] = m / T(n1 * n2);
     }
   }
@@ -158,24 +234,25 @@ void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, i
 template <class T>
 void launch_sync(int ndim, int R, const GridDesc* grids, const SyncTables& t, const T* freg, const T* ereg,
                  DevState<T> Uf, DevState<T> Uc, hipStream_t s) {
+  (void)R;  // the kernels are unrolled over kR; the caller checks R == kR
   if (t.n_reflux > 0) {
     if (ndim == 3)
       hipLaunchKernelGGL((k_reflux<T, 3>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
-                         t.nfreg, R, Uc);
+                         t.nfreg, Uc);
     else
       hipLaunchKernelGGL((k_reflux<T, 2>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
-                         t.nfreg, R, Uc);
+                         t.nfreg, Uc);
   }
   if (t.n_emffix > 0)
     hipLaunchKernelGGL((k_emffix<T>), dim3(blocks_for(t.n_emffix)), dim3(256), 0, s, t.d_emffix, t.n_emffix, ereg,
-                       t.nereg, R, Uc);
+                       t.nereg, Uc);
   if (t.n_restrict > 0) {
     if (ndim == 3)
       hipLaunchKernelGGL((k_restrict<T, 3>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
-                         t.n_restrict, grids, R, Uf, Uc);
+                         t.n_restrict, grids, Uf, Uc);
     else
       hipLaunchKernelGGL((k_restrict<T, 2>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
-                         t.n_restrict, grids, R, Uf, Uc);
+                         t.n_restrict, grids, Uf, Uc);
   }
 }
 
