@@ -386,7 +386,7 @@ def main():
                     help="largest box extent of the measured regrid, in level-1 cells")
     ap.add_argument("--launch-config", default=None,
                     help="tile_policy,zchunk,launch_mode[,update_zchunk]: set this launch configuration instead "
-                         "of autotuning (launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD)")
+                         "of autotuning (launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD, bit 2 persistent flux kernel only)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")

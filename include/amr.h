@@ -314,9 +314,11 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * bit 1: the item list is cut into 8 contiguous chunks, one per XCD
  * (workgroups reach the XCDs round-robin, so chunk c runs on XCD c and
  * neighbouring tiles share its L2; persistent blocks drain their own chunk
- * first, then the others).  Results do not depend on the configuration
- * (bitwise).  Changing tile_policy or zchunk rebuilds the work lists and
- * drops captured graphs.  Default: 1, 16, 0. */
+ * first, then the others); bit 2: persistent launches of the flux kernel
+ * only, the update one block per item (implied for the flux kernel by bit 0;
+ * launch_mode in [0, 7], else AMR_EINVAL).  Results do not depend on the
+ * configuration (bitwise).  Changing tile_policy or zchunk rebuilds the work
+ * lists and drops captured graphs.  Default: 1, 16, 0. */
 amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
 
@@ -329,7 +331,7 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
 amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk);
 amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk);
 
-#define AMR_TUNE_CANDIDATES 36
+#define AMR_TUNE_CANDIDATES 52
 
 typedef struct {
   int32_t tile_policy, zchunk, launch_mode, update_zchunk;
@@ -338,12 +340,12 @@ typedef struct {
 
 /* Autotuner of the batched advance: fills every level's band (FULL, coarse
  * to fine) and computes dt0 (both redone by the next coarse step), then
- * times the 32 configurations tile_policy x zchunk in {8, 16, 32, 64} x
- * launch_mode in [0, 3] (entries 0..31, under the current update z-chunk),
- * keeps the fastest, and under it times the update z-chunks {1, 2, 4, 8}
- * (entries 32..35), each over `reps` passes of every launch cycle's batched
- * advance, reading each level's current buffer (parity) and writing the
- * other one, and keeps the fastest of all 36.  The state the
+ * times the 48 configurations tile_policy x zchunk in {8, 12, 16, 32} x
+ * launch_mode in {0, 1, 2, 3, 4, 6} (entries 0..47, under the current update
+ * z-chunk), keeps the fastest, and under it times the update z-chunks
+ * {1, 2, 4, 8} (entries 48..51), each over `reps` passes of every launch
+ * cycle's batched advance, reading each level's current buffer (parity) and
+ * writing the other one, and keeps the fastest of all 52.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */

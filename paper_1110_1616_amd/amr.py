@@ -275,7 +275,8 @@ def amr_advance_frozen(h, level, dts, Ubase, Upert, ws):
 
 
 def amr_set_launch_config(h, tile_policy, zchunk, launch_mode):
-    """launch_mode bit 0: persistent queue; bit 1: one item chunk per XCD."""
+    """launch_mode bit 0: persistent queue; bit 1: one item chunk per XCD;
+    bit 2: persistent flux kernel only."""
     _check(lib().amr_set_launch_config(h, tile_policy, zchunk, int(launch_mode)), "amr_set_launch_config")
 
 
@@ -295,7 +296,7 @@ def amr_get_update_zchunk(h):
     return a.value
 
 
-TUNE_CANDIDATES = 36
+TUNE_CANDIDATES = 52
 
 
 def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):

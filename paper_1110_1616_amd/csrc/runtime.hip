@@ -147,6 +147,7 @@ struct amr_hierarchy {
   int upd_zchunk = 2;  // planes per update / edge-EMF work item (the update prefers short ones)
   int tile_policy = 1;  // 0: 16 x 16 tiles; 1: per-grid width with the fewest tiles
   bool persistent = false;     // persistent launches popping d_queue, or one block per item
+  bool persistent_flux = false;  // the flux kernel persistent (implied by `persistent`)
   bool xcd_chunks = false;     // item lists cut into one contiguous chunk per XCD
   WorkQueue* d_queue = nullptr;
   int flux_pblocks = 0, upd_pblocks = 0;  // persistent grid sizes (resident blocks on the device)
@@ -1235,7 +1236,7 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
-                 h->d_queue, h->persistent ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
+                 h->d_queue, h->persistent_flux ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
@@ -1842,8 +1843,9 @@ void set_update_zchunk(amr_hierarchy* h, int zchunk) {
 void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
   if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
-  if (mode < 0 || mode > 3) throw Error(AMR_EINVAL, "launch mode must be in [0, 3]");
+  if (mode < 0 || mode > 7) throw Error(AMR_EINVAL, "launch mode must be in [0, 7]");
   h->persistent = (mode & 1) != 0;
+  h->persistent_flux = (mode & 5) != 0;
   h->xcd_chunks = (mode & 2) != 0;
   if (policy != h->tile_policy || zchunk != h->zchunk) {
     h->tile_policy = policy;
@@ -1887,21 +1889,24 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
     do_fill<T>(h, l, l > 0 ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur, par, s);
   }
   do_dt<T>(h, Ua, Ub, parity, dt0, s);
-  const int zc[4] = {8, 16, 32, 64};
-  int best = -1, n = 0;
+  const int zc[4] = {8, 12, 16, 32};
+  const int modes[6] = {0, 1, 2, 3, 4, 6};
+  int best = -1, n = 0, bpol = 1, bzc = 8, bmode = 0;
   double best_ms = 0.0;
   for (int pol = 0; pol < 2; ++pol)
     for (int zi = 0; zi < 4; ++zi)
-      for (int mode = 0; mode < 4; ++mode, ++n) {
-        set_launch_config(h, pol, zc[zi], mode);
+      for (int mi = 0; mi < 6; ++mi, ++n) {
+        set_launch_config(h, pol, zc[zi], modes[mi]);
         const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
-        if (out) out[n] = amr_tune_entry{pol, zc[zi], mode, h->upd_zchunk, ms};
+        if (out) out[n] = amr_tune_entry{pol, zc[zi], modes[mi], h->upd_zchunk, ms};
         if (best < 0 || ms < best_ms) {
           best = n;
           best_ms = ms;
+          bpol = pol;
+          bzc = zc[zi];
+          bmode = modes[mi];
         }
       }
-  const int bpol = (best >> 4) & 1, bzc = zc[(best >> 2) & 3], bmode = best & 3;
   set_launch_config(h, bpol, bzc, bmode);
   // then the update's planes per item, under the kept configuration
   const int uzc[4] = {1, 2, 4, 8};
@@ -2317,7 +2322,8 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
   if (!h) return AMR_EINVAL;
   if (tile_policy) *tile_policy = h->tile_policy;
   if (zchunk) *zchunk = h->zchunk;
-  if (launch_mode) *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0);
+  if (launch_mode)
+    *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0) | (h->persistent_flux && !h->persistent ? 4 : 0);
   return AMR_OK;
 }
 

@@ -136,16 +136,16 @@ def test_graph_replay_matches_eager_every_replay():
 
 @pytest.mark.parametrize("key", ["3d", "2d"])
 def test_every_launch_configuration_gives_identical_results(key):
-    """Tile policy, z-chunk, persistent vs one-block-per-item launches, XCD
-    chunking and the update's z-chunk only change how the same per-face and
-    per-cell arithmetic is distributed: two coarse steps agree bit for bit
-    under all 32 configurations (each with one of the update z-chunks 1, 2,
-    3, 8, all four met under each launch mode)."""
+    """Tile policy, z-chunk, persistent vs one-block-per-item launches (both
+    kernels or the flux kernel only), XCD chunking and the update's z-chunk
+    only change how the same per-face and per-cell arithmetic is
+    distributed: two coarse steps agree bit for bit under all 48
+    configurations (each with one of the update z-chunks 1, 2, 3, 8)."""
     ndim, N0, L, grids, fields = _setup(key)
     ref = None
     for pol in (0, 1):
-        for zi, zc in enumerate((8, 16, 32, 64)):
-            for per in (0, 1, 2, 3):
+        for zi, zc in enumerate((8, 12, 16, 64)):
+            for per in (0, 1, 2, 3, 4, 6):
                 uz = (1, 2, 3, 8)[(zi + per) % 4]
                 log(f"case: launch config {key} policy={pol} zchunk={zc} mode={per} update zchunk={uz}")
                 H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
@@ -169,7 +169,7 @@ def test_every_launch_configuration_gives_identical_results(key):
 
 
 def test_autotune_keeps_the_state_and_the_results():
-    """The autotuner times all 32 launch configurations and then the update
+    """The autotuner times all 48 launch configurations and then the update
     z-chunks under the fastest, without changing what the next coarse step
     computes."""
     import torch
@@ -185,8 +185,8 @@ def test_autotune_keeps_the_state_and_the_results():
     assert 0 <= chosen < A.TUNE_CANDIDATES and all(t[3] > 0 for t in table)
     assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
     assert A.amr_get_update_zchunk(H.h) == table[chosen][4]
-    assert [t[4] for t in table[32:]] == [1, 2, 4, 8]
-    assert all(tuple(t[:3]) == tuple(table[32][:3]) for t in table[32:])
+    assert [t[4] for t in table[48:]] == [1, 2, 4, 8]
+    assert all(tuple(t[:3]) == tuple(table[48][:3]) for t in table[48:])
     par = H.coarse_step(Ua, Ub, par, 0)
     torch.cuda.synchronize()
     got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]

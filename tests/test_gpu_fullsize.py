@@ -29,9 +29,9 @@ def test_amr3_full_size_graph_replay_matches_oracle():
     N0, L = (112, 112, 112), 3
     grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
     fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
-    log(f"case: 3-level hierarchy base 112^3, {len(grids)} grids, launch config 1,8,2, eta schedule, graph replay")
+    log(f"case: 3-level hierarchy base 112^3, {len(grids)} grids, launch config 1,12,6,2, eta schedule, graph replay")
     H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4)
-    H.set_launch_config(1, 8, 2)
+    H.set_launch_config(1, 12, 6, 2)
     H.set_schedule(1)
     Ua, Ub = H.new_state(), H.new_state()
     stream = torch.cuda.Stream()
