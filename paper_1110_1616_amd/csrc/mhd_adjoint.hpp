@@ -13,18 +13,18 @@ namespace amr {
 template <class T>
 __host__ __device__ __forceinline__ void fast_magnetosonic_adj(T r, T p, T b2, T bn, T gam, T a_cf, T& a_r, T& a_p,
                                                                T& a_b2, T& a_bn) {
-  const T ir = T(1) / r;
+  const T ir = drcp(r);
   const T gp = gam * p;
   const T a = (gp + b2) * ir;
   const T d0 = a * a - T(4) * gp * bn * bn * ir * ir;
   const bool pos = d0 > T(0);
   const T d = pos ? d0 : T(0);
-  const T sd = dsqrt(d);
-  const T cf = dsqrt(T(0.5) * (a + sd));
-  const T a_cf2 = a_cf * T(0.5) / cf;
+  const T sd = psqrt(d);
+  const T cf = psqrt(T(0.5) * (a + sd));
+  const T a_cf2 = a_cf * T(0.5) * drcp(cf);
   T a_a = T(0.5) * a_cf2;
   const T a_sd = T(0.5) * a_cf2;
-  const T a_d0 = (pos && sd > T(0)) ? a_sd * T(0.5) / sd : T(0);
+  const T a_d0 = (pos && sd > T(0)) ? a_sd * T(0.5) * drcp(sd) : T(0);
   a_a += T(2) * a * a_d0;
   T a_gp = -T(4) * bn * bn * ir * ir * a_d0;
   a_bn += -T(8) * gp * bn * ir * ir * a_d0;
@@ -39,7 +39,7 @@ __host__ __device__ __forceinline__ void fast_magnetosonic_adj(T r, T p, T b2, T
 // to_primitive(u -> w): a_u += (dw/du)^T a_w.
 template <class T>
 __host__ __device__ __forceinline__ void to_primitive_adj(const T (&u)[8], T gm1, const T (&a_w)[8], T (&a_u)[8]) {
-  const T ir = T(1) / u[0];
+  const T ir = drcp(u[0]);
   const T w1 = u[1] * ir, w2 = u[2] * ir, w3 = u[3] * ir;
   const T v2 = w1 * w1 + w2 * w2 + w3 * w3;
   a_u[4] += gm1 * a_w[4];
@@ -137,7 +137,7 @@ template <class T>
 __host__ __device__ void riemann_hlld_adj(const T (&ql)[8], const T (&qr)[8], T bn, T gam, const T (&a_f)[7],
                                           T (&a_ql)[8], T (&a_qr)[8], T& a_bn) {
   // ---------------- forward (same arithmetic as riemann_hlld) ----------------
-  const T g1i = T(1) / (gam - T(1));
+  const T g1i = drcp(gam - T(1));
   const T bn2 = bn * bn;
   const T rl = ql[0], ul = ql[1], vl = ql[2], wl = ql[3], pl = ql[4], byl = ql[6], bzl = ql[7];
   const T rr = qr[0], ur = qr[1], vr = qr[2], wr = qr[3], pr = qr[4], byr = qr[6], bzr = qr[7];
@@ -161,7 +161,7 @@ __host__ __device__ void riemann_hlld_adj(const T (&ql)[8], const T (&qr)[8], T 
   const T rdl = rl * dl, rdr = rr * dr;
   const T num = rdr * ur - rdl * ul - ptr + ptl;
   const T den = rdr - rdl;
-  const T sm = num / den;
+  const T sm = num * drcp(den);
   const T pts = ptl + rdl * (sm - ul);
   const T tiny = T(1e-12) * pts;
 
@@ -174,11 +174,11 @@ __host__ __device__ void riemann_hlld_adj(const T (&ql)[8], const T (&qr)[8], T 
     o.d = s - u;
     o.rd = rd;
     o.dsm = s - sm;
-    o.idsm = T(1) / o.dsm;
+    o.idsm = drcp(o.dsm);
     o.rs = rd * o.idsm;
     o.dn = rd * o.dsm - bn2;
     o.deg = dabs(o.dn) <= tiny;
-    o.idn = o.deg ? T(0) : T(1) / o.dn;
+    o.idn = o.deg ? T(0) : drcp(o.dn);
     o.smu = sm - u;
     o.fv = bn * o.smu * o.idn;
     o.qq = rd * o.d - bn2;
@@ -196,14 +196,14 @@ __host__ __device__ void riemann_hlld_adj(const T (&ql)[8], const T (&qr)[8], T 
   };
   const Side L = star(rl, ul, vl, wl, byl, bzl, el, ptl, sl, rdl);
   const Side R = star(rr, ur, vr, wr, byr, bzr, er, ptr, sr, rdr);
-  const T sql = dsqrt(L.rs), sqr = dsqrt(R.rs);
+  const T sql = psqrt(L.rs), sqr = psqrt(R.rs);
   const T sb = bn < T(0) ? T(-1) : T(1);  // d|bn|/dbn
   const T abn = dabs(bn);
-  const T ssl = sm - abn / sql;
-  const T ssr = sm + abn / sqr;
+  const T ssl = sm - abn * drcp(sql);
+  const T ssr = sm + abn * drcp(sqr);
   const bool ddeg = T(0.5) * bn2 <= tiny;
   const T sg = bn > T(0) ? T(1) : T(-1);
-  const T isum = T(1) / (sql + sqr);
+  const T isum = drcp(sql + sqr);
   const T nv = sql * L.vs + sqr * R.vs + (R.bys - L.bys) * sg;
   const T nw = sql * L.ws + sqr * R.ws + (R.bzs - L.bzs) * sg;
   const T nby = sql * R.bys + sqr * L.bys + sql * sqr * (R.vs - L.vs) * sg;
