@@ -168,6 +168,21 @@ def test_every_launch_configuration_gives_identical_results(key):
                         assert np.array_equal(x, y)
 
 
+def test_launch_configuration_rejects_bad_values():
+    """Out-of-range tile policy, z-chunks and launch modes are refused and
+    leave the configuration as it was."""
+    ndim, N0, L, grids, fields = _setup("3d")
+    H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
+    H.set_launch_config(1, 12, 6, 2)
+    for bad in ((2, 8, 0), (1, 0, 0), (1, 8, 8), (1, 8, -1)):
+        with pytest.raises(A.AmrError):
+            A.amr_set_launch_config(H.h, *bad)
+    with pytest.raises(A.AmrError):
+        A.amr_set_update_zchunk(H.h, 0)
+    assert A.amr_get_launch_config(H.h) == (1, 12, 6)
+    assert A.amr_get_update_zchunk(H.h) == 2
+
+
 def test_autotune_keeps_the_state_and_the_results():
     """The autotuner times all 48 launch configurations and then the update
     z-chunks under the fastest, without changing what the next coarse step
