@@ -28,13 +28,15 @@ namespace {
 // side: (tw+2) x (th+2) entries, at most kMaxPlane.
 constexpr int kMaxPlane = 396;  // max over tw in [4, 64] of (tw + 2)(256 / tw + 2)
 
-// Ring entry r in [0, 2(tw+2) + 2 th) of the plane -> (ex, ey).
+// Ring entry r in [0, 2 (tw + th)) of the plane -> (ex, ey): the one-cell
+// border of the tile's (tw + 2) x (th + 2) LDS plane without its four
+// corners, which no cell reads (the slopes use the x and y neighbours only).
+// A 16 x 16 tile's 64 ring cells are then one wave's lanes.
 __device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& ey) {
-  const int w2 = tw + 2;
-  if (r < w2) { ex = r; ey = 0; }
-  else if (r < 2 * w2) { ex = r - w2; ey = th + 1; }
-  else if (r < 2 * w2 + th) { ex = 0; ey = r - 2 * w2 + 1; }
-  else { ex = tw + 1; ey = r - 2 * w2 - th + 1; }
+  if (r < tw) { ex = r + 1; ey = 0; }
+  else if (r < 2 * tw) { ex = r - tw + 1; ey = th + 1; }
+  else if (r < 2 * tw + th) { ex = 0; ey = r - 2 * tw + 1; }
+  else { ex = tw + 1; ey = r - 2 * tw - th + 1; }
 }
 
 // Next work item of this block.  Grid-stride launches take blockIdx.x,
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
 
     // own LDS entry and (for the first nring threads) one ring entry
     const int eo = (ty + 1) * kW + tx + 1;
-    const int nring = 2 * (tw + 2) + 2 * th;
+    const int nring = 2 * (tw + th);
     int rex = 0, rey = 0;
     if (tid < nring) ring_entry(tid, tw, th, rex, rey);
     const int rcx = x0 - 2 + rex, rcy = y0 - 2 + rey;
