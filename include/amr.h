@@ -309,8 +309,10 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * per tile) that launches the fewest tiles over the grid.  zchunk: planes per
  * work item along z (3D).  launch_mode bit 0: persistent launches (a fixed
  * grid of resident blocks popping the launch's item list from a device
- * queue, one atomic per item, list order = finest level first; the queue
- * resets itself at the end of each launch), else one block per work item;
+ * queue, one atomic per item, in list order: finest level first, then inside
+ * each eighth of the flux list its longest items (most z-planes) first; the
+ * queue resets itself at the end of each launch), else one block per work
+ * item;
  * bit 1: the item list is cut into 8 contiguous chunks, one per XCD
  * (workgroups reach the XCDs round-robin, so chunk c runs on XCD c and
  * neighbouring tiles share its L2; persistent blocks drain their own chunk

@@ -417,6 +417,16 @@ LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& g
   L.emf.n = (int)h->h_eitems.size() - L.emf.off;
   L.flux.n = (int)h->h_fitems.size() - L.flux.off;
   L.upd.n = (int)h->h_uitems.size() - L.upd.off;
+  // longest flux items first inside each eighth of the list (the XCD chunks
+  // of the launch): blocks take items in list order, so the short ones
+  // (a grid's last z-chunk) fill the end of the launch instead of starting
+  // late; items stay in their chunk, next to the tiles they share halos with
+  const int C = (L.flux.n + 7) / 8;
+  for (int c = 0; c < 8 && c * C < L.flux.n; ++c) {
+    auto b = h->h_fitems.begin() + L.flux.off + c * C;
+    auto e = h->h_fitems.begin() + L.flux.off + std::min(L.flux.n, (c + 1) * C);
+    std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
+  }
   return L;
 }
 
