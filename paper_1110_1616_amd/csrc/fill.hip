@@ -5,6 +5,8 @@
 // images and outflow boundaries) and, for FULL fills above level 0,
 // prolongation maps that name the coarse cell or face each band element is
 // reconstructed from.  Every band element has exactly one writer.
+#include <algorithm>
+
 #include "amr_internal.hpp"
 #include "fill_internal.hpp"
 #include "frozen.hpp"
@@ -128,10 +130,10 @@ __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __res
 }
 
 // ------------------------------------------------------------------- CFL
-// Max over interior cells of sum_d (|v_d| + c_f,d) / dx0_d; one block per
-// (grid, plane) item.  Wavefront max by lane exchange, then LDS across the
-// four waves, then one atomic max on the bit pattern of the non-negative
-// double (order independent, hence deterministic).
+// Max over interior cells of sum_d (|v_d| + c_f,d) / dx0_d; blocks stride
+// over (grid, plane, rows) items.  Wavefront max by lane exchange, then LDS
+// across the four waves, then one atomic max per block on the bit pattern of
+// the non-negative double (order independent, hence deterministic).
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -145,6 +147,9 @@ __global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids,
   __shared__ double red[4];
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
+  // a few blocks per CU stride over the items; each thread keeps its
+  // running max and the block reduces once at the end (one atomic per block)
+  double m = 0.0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     // item: (grid, plane k, first row j0, rows)
     const int4 item = items[it];
@@ -155,7 +160,6 @@ __global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids,
     const int64_t base = G.off + G.g + G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0) + (int64_t)k * sz +
                          (int64_t)item.z * sy;
     const int ncell = G.n[0] * item.w;
-    double m = 0.0;
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
       const int i = c % G.n[0], j = c / G.n[0];
       const int64_t e = base + i + j * sy;
@@ -182,14 +186,13 @@ __global__ __launch_bounds__(256) void k_cfl(const GridDesc* __restrict__ grids,
       }
       m = fmax(m, s);
     }
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double b = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-      atomicMax(acc, (unsigned long long)__double_as_longlong(b));
-    }
-    __syncthreads();
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(acc, (unsigned long long)__double_as_longlong(b));
   }
 }
 
@@ -310,17 +313,19 @@ void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const Prolo
   }
 }
 
+constexpr int kCflBlocks = 2048;  // 8 per CU on 256 CUs
+
 template <class T>
 void launch_cfl(int ndim, const GridDesc* grids, const int4* items, int nitems, DevState<T> S0, DevState<T> S1,
                 uint32_t parity, Phys ph, unsigned long long* acc, ErrBlock* err, double cfl, double* dt0,
                 hipStream_t s) {
   if (nitems > 0) {
     if (ndim == 3)
-      hipLaunchKernelGGL((k_cfl<T, 3>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, ph, acc,
-                         err);
+      hipLaunchKernelGGL((k_cfl<T, 3>), dim3(std::min(nitems, kCflBlocks)), dim3(256), 0, s, grids, items, nitems, S0,
+                         S1, parity, ph, acc, err);
     else
-      hipLaunchKernelGGL((k_cfl<T, 2>), dim3(nitems), dim3(256), 0, s, grids, items, nitems, S0, S1, parity, ph, acc,
-                         err);
+      hipLaunchKernelGGL((k_cfl<T, 2>), dim3(std::min(nitems, kCflBlocks)), dim3(256), 0, s, grids, items, nitems, S0,
+                         S1, parity, ph, acc, err);
   }
   hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(64), 0, s, acc, cfl, dt0);
 }
