@@ -23,60 +23,64 @@ inline int blocks_for(int64_t n) {
 // definition states (one memory latency per thread instead of one per term).
 constexpr int kR = 2;
 
+// Coarse/fine registers of one substep, both kinds in one launch: entries
+// [0, nf) are face registers, [nf, nf + ne) edge registers.
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_reg_faces(const FaceRegEntry* __restrict__ ent, int n, DevFlux<T> F,
-                                                   T* __restrict__ reg, int nreg, int slot,
-                                                   const double* __restrict__ dt0p, double dt_div) {
-  const T dt = T(dt0p[0] / dt_div);
+__device__ __forceinline__ void reg_face(const FaceRegEntry& e, const DevFlux<T>& F, T* __restrict__ reg, int nreg,
+                                         int slot, T dt) {
   constexpr int ns = NDIM == 2 ? 6 : 5;
   constexpr int nmax = NDIM == 3 ? kR * kR : kR;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const FaceRegEntry e = ent[t];
-    T* out = reg + ((int64_t)slot * nreg + e.reg) * 6;
-    T v[ns][nmax];
+  T* out = reg + ((int64_t)slot * nreg + e.reg) * 6;
+  T v[ns][nmax];
 #pragma unroll
-    for (int q = 0; q < ns; ++q) {
-      const int s = q < 5 ? q : 7;
-      const T* f = F.f[e.d][flux_comp(s, e.d)];
+  for (int q = 0; q < ns; ++q) {
+    const int s = q < 5 ? q : 7;
+    const T* f = F.f[e.d][flux_comp(s, e.d)];
 #pragma unroll
-      for (int i = 0; i < nmax; ++i) v[q][i] = i < e.n ? f[e.e[i]] : T(0);
-    }
+    for (int i = 0; i < nmax; ++i) v[q][i] = i < e.n ? f[e.e[i]] : T(0);
+  }
 #pragma unroll
-    for (int q = 0; q < ns; ++q) {
-      T m = T(0);
+  for (int q = 0; q < ns; ++q) {
+    T m = T(0);
 #pragma unroll
-      for (int i = 0; i < nmax; ++i)
-        if (i < e.n) m += v[q][i];
-      out[q] = dt * (m / T(e.n));
-    }
+    for (int i = 0; i < nmax; ++i)
+      if (i < e.n) m += v[q][i];
+    out[q] = dt * (m / T(e.n));
   }
 }
 
 template <class T, int NDIM, bool UPWIND>
-__global__ __launch_bounds__(256) void k_reg_edges(const EdgeRegEntry* __restrict__ ent, int n,
-                                                   const GridDesc* __restrict__ grids, DevFlux<T> F,
-                                                   T* __restrict__ reg, int nreg, int slot,
-                                                   const double* __restrict__ dt0p, double dt_div) {
-  const T dt = T(dt0p[0] / dt_div);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const EdgeRegEntry e = ent[t];
-    const GridDesc G = grids[e.grid];
-    const int64_t st[3] = {1, G.P[0], NDIM == 3 ? (int64_t)G.P[0] * G.P[1] : 0};
-    T v[kR];
+__device__ __forceinline__ void reg_edge(const EdgeRegEntry& e, const GridDesc* __restrict__ grids,
+                                         const DevFlux<T>& F, T* __restrict__ reg, int nreg, int slot, T dt) {
+  const GridDesc G = grids[e.grid];
+  const int64_t st[3] = {1, G.P[0], NDIM == 3 ? (int64_t)G.P[0] * G.P[1] : 0};
+  T v[kR];
 #pragma unroll
-    for (int i = 0; i < kR; ++i) {
-      v[i] = T(0);
-      if (i < e.n) {
-        if (e.a == 0) v[i] = emf_at<0, UPWIND>(F, e.e[i], st);
-        else if (e.a == 1) v[i] = emf_at<1, UPWIND>(F, e.e[i], st);
-        else v[i] = emf_at<2, UPWIND>(F, e.e[i], st);
-      }
+  for (int i = 0; i < kR; ++i) {
+    v[i] = T(0);
+    if (i < e.n) {
+      if (e.a == 0) v[i] = emf_at<0, UPWIND>(F, e.e[i], st);
+      else if (e.a == 1) v[i] = emf_at<1, UPWIND>(F, e.e[i], st);
+      else v[i] = emf_at<2, UPWIND>(F, e.e[i], st);
     }
-    T m = T(0);
+  }
+  T m = T(0);
 #pragma unroll
-    for (int i = 0; i < kR; ++i)
-      if (i < e.n) m += v[i];
-    reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
+  for (int i = 0; i < kR; ++i)
+    if (i < e.n) m += v[i];
+  reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
+}
+
+template <class T, int NDIM, bool UPWIND>
+__global__ __launch_bounds__(256) void k_registers(const FaceRegEntry* __restrict__ fe, int nf,
+                                                   const EdgeRegEntry* __restrict__ ee, int ne,
+                                                   const GridDesc* __restrict__ grids, DevFlux<T> F,
+                                                   T* __restrict__ freg, int nfreg, T* __restrict__ ereg, int nereg,
+                                                   int slot, const double* __restrict__ dt0p, double dt_div) {
+  const T dt = T(dt0p[0] / dt_div);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nf + ne; t += gridDim.x * blockDim.x) {
+    if (t < nf) reg_face<T, NDIM>(fe[t], F, freg, nfreg, slot, dt);
+    else reg_edge<T, NDIM, UPWIND>(ee[t - nf], grids, F, ereg, nereg, slot, dt);
   }
 }
 
@@ -208,27 +212,18 @@ template <class T>
 void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
                       DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
                       double dt_div, bool upwind_emf, hipStream_t s) {
-  if (nf > 0) {
-    if (ndim == 3)
-      hipLaunchKernelGGL((k_reg_faces<T, 3>), dim3(blocks_for(nf)), dim3(256), 0, s, fe, nf, F, freg, nfreg, slot, dt0,
-                         dt_div);
-    else
-      hipLaunchKernelGGL((k_reg_faces<T, 2>), dim3(blocks_for(nf)), dim3(256), 0, s, fe, nf, F, freg, nfreg, slot, dt0,
-                         dt_div);
+  if (nf + ne <= 0) return;
+#define AMR_REGS(ND, U)                                                                                            \
+  hipLaunchKernelGGL((k_registers<T, ND, U>), dim3(blocks_for((int64_t)nf + ne)), dim3(256), 0, s, fe, nf, ee, ne, \
+                     grids, F, freg, nfreg, ereg, nereg, slot, dt0, dt_div)
+  if (ndim == 3) {
+    if (upwind_emf) AMR_REGS(3, true);
+    else AMR_REGS(3, false);
+  } else {
+    if (upwind_emf) AMR_REGS(2, true);
+    else AMR_REGS(2, false);
   }
-  if (ne > 0) {
-#define AMR_REG_EDGES(ND, U)                                                                                       \
-  hipLaunchKernelGGL((k_reg_edges<T, ND, U>), dim3(blocks_for(ne)), dim3(256), 0, s, ee, ne, grids, F, ereg, nereg, \
-                     slot, dt0, dt_div)
-    if (ndim == 3) {
-      if (upwind_emf) AMR_REG_EDGES(3, true);
-      else AMR_REG_EDGES(3, false);
-    } else {
-      if (upwind_emf) AMR_REG_EDGES(2, true);
-      else AMR_REG_EDGES(2, false);
-    }
-#undef AMR_REG_EDGES
-  }
+#undef AMR_REGS
 }
 
 template <class T>
