@@ -71,6 +71,8 @@ __device__ __forceinline__ void reg_edge(const EdgeRegEntry& e, const GridDesc* 
   reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
 }
 
+// The face and edge registers of one fine step in one launch: threads
+// [0, nf) take face entries, [nf, nf + ne) edge entries.
 template <class T, int NDIM, bool UPWIND>
 __global__ __launch_bounds__(256) void k_registers(const FaceRegEntry* __restrict__ fe, int nf,
                                                    const EdgeRegEntry* __restrict__ ee, int ne,
