@@ -12,6 +12,7 @@
 // are the initial cell density and velocity (pressure and face B fixed); the
 // loss is the kinetic energy sum over cells c in a box S of |m_c|^2/(2 rho_c)
 // times the cell volume after the last step.
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -460,6 +461,145 @@ int orc_step_vjp(int ndim, const int* n, double gamma, double dt, const double* 
           for (int i = 0; i < iext(L, s, 0); ++i)
             lam_in[s][iidx(L, s, i, j, k)] = adj[ids[s][L.idx(s, i, j, k)]];
     g_tape.clear();
+    return 0;
+  } catch (const std::exception& e) {
+    j_err = e.what();
+    g_tape.clear();
+    return -1;
+  }
+}
+
+
+// Vector-Jacobian product of one substep of every grid of one level, the
+// batched level map of the adjoint: each grid's band is first refreshed by
+// the same-level copy -- a band cell lying in a grid's interior, or a band
+// face lying in or on the boundary of one (periodic images included), takes
+// that element of the lowest-index such grid -- and every other band
+// element (the prolonged part) is a constant of the map; then every grid
+// takes one band-2 step of size dt (Sec. 1 and the abstract: the grid's
+// advance reads nothing but its own band).  The own elements of a grid are
+// its cells [0, n) and its faces [0, n] along their normal ([0, n) across);
+// a face shared by two grids is an own element of both.
+//   Nl: the level's cells per axis (periodic); boxes: ngrids x (lo[3],
+//   hi[3]) in level cells; banded: ngrids*8 pointers, each grid's state in
+//   the oracle's banded layout with band g (constant band values and own
+//   values are read here); sel[0..nsel): the grids whose output adjoint is
+//   given (lam_out: nsel*8 interior-layout pointers; zero on other grids);
+//   lam_in: ngrids*8 interior-layout pointers, the adjoint of the input on
+//   every grid's own elements (written in full).
+int orc_level_vjp(int ndim, const int* Nl, int g, double gamma, const double* dx, double dt, int ngrids,
+                  const int* boxes, const double* const* banded, int nsel, const int* sel,
+                  const double* const* lam_out, double* const* lam_in) {
+  try {
+    if (g < 2) throw std::runtime_error("band too narrow");
+    std::vector<Layout> Ls(ngrids);
+    for (int G = 0; G < ngrids; ++G) {
+      int n[3];
+      for (int a = 0; a < 3; ++a) n[a] = a < ndim ? boxes[6 * G + 3 + a] - boxes[6 * G + a] : 1;
+      Ls[G] = lay(ndim, n, g);
+      for (int s = 0; s < NVAR; ++s) {
+        size_t m = (size_t)iext(Ls[G], s, 0) * iext(Ls[G], s, 1) * iext(Ls[G], s, 2);
+        std::fill(lam_in[8 * G + s], lam_in[8 * G + s] + m, 0.0);
+      }
+    }
+    auto lo = [&](int G, int a) { return a < ndim ? boxes[6 * G + a] : 0; };
+    auto hi = [&](int G, int a) { return a < ndim ? boxes[6 * G + 3 + a] : 1; };
+    auto wrap = [&](int (&p)[3]) {
+      for (int a = 0; a < ndim; ++a) p[a] = ((p[a] % Nl[a]) + Nl[a]) % Nl[a];
+    };
+    // grid whose interior holds the (wrapped) level cell p, or -1
+    auto owner = [&](const int (&p)[3]) {
+      for (int H = 0; H < ngrids; ++H) {
+        bool in = true;
+        for (int a = 0; a < 3; ++a) in = in && p[a] >= lo(H, a) && p[a] < hi(H, a);
+        if (in) return H;
+      }
+      return -1;
+    };
+    // source (grid, local index) of element (s, level position p) under the
+    // same-level copy, or false
+    auto source = [&](int s, const int (&p)[3], int& H, int (&loc)[3]) {
+      const bool face = Ls[0].is_face(s);
+      const int d = s - 5;
+      H = -1;
+      for (int side = 0; side < (face ? 2 : 1); ++side) {
+        int c[3] = {p[0], p[1], p[2]};
+        if (side == 1) c[d] -= 1;
+        wrap(c);
+        const int w = owner(c);
+        if (w < 0 || (H >= 0 && w >= H)) continue;
+        H = w;
+        for (int a = 0; a < 3; ++a) loc[a] = c[a] - lo(w, a);
+        if (side == 1) loc[d] += 1;
+      }
+      return H >= 0;
+    };
+    StepParams P{gamma, {dx[0], dx[1], ndim == 3 ? dx[2] : 1.0}, 0};
+    for (int t = 0; t < nsel; ++t) {
+      const int G = sel[t];
+      if (G < 0 || G >= ngrids) throw std::runtime_error("selected grid out of range");
+      const Layout& L = Ls[G];
+      g_tape.clear();
+      // tape variables of this pass: (grid, slot, interior index) -> node
+      std::vector<std::vector<int32_t>> ids((size_t)ngrids * NVAR);
+      auto var = [&](int H, int s, const int (&q)[3]) {
+        std::vector<int32_t>& v = ids[(size_t)H * NVAR + s];
+        if (v.empty()) v.assign((size_t)iext(Ls[H], s, 0) * iext(Ls[H], s, 1) * iext(Ls[H], s, 2), -1);
+        const size_t e = iidx(Ls[H], s, q[0], q[1], q[2]);
+        if (v[e] < 0) v[e] = g_tape.push(-1, 0.0, -1, 0.0);
+        const double val = banded[8 * H + s][Ls[H].idx(s, q[0], q[1], q[2])];
+        return Adj(v[e], val);
+      };
+      State<Adj> S(L), O(L);
+      for (int s = 0; s < NVAR; ++s) {
+        const bool face = L.is_face(s);
+        for (int k = -L.gd(2); k < L.n[2] + L.gd(2) + ((face && s == 7) ? 1 : 0); ++k)
+          for (int j = -L.gd(1); j < L.n[1] + L.gd(1) + ((face && s == 6) ? 1 : 0); ++j)
+            for (int i = -L.gd(0); i < L.n[0] + L.gd(0) + ((face && s == 5) ? 1 : 0); ++i) {
+              const int x[3] = {i, j, k};
+              bool own = true;
+              for (int a = 0; a < ndim; ++a) {
+                const int top = (face && s - 5 == a) ? L.n[a] : L.n[a] - 1;
+                own = own && x[a] >= 0 && x[a] <= top;
+              }
+              if (own) {
+                S.at(s, i, j, k) = var(G, s, x);
+                continue;
+              }
+              int p[3] = {lo(G, 0) + i, lo(G, 1) + j, lo(G, 2) + k}, H, loc[3];
+              if (source(s, p, H, loc))
+                S.at(s, i, j, k) = var(H, s, loc);
+              else
+                S.at(s, i, j, k) = Adj(banded[8 * G + s][L.idx(s, i, j, k)]);
+            }
+      }
+      step(S, O, 2, Adj(dt), P);
+      std::vector<double> adj(g_tape.a.size(), 0.0);
+      for (int s = 0; s < NVAR; ++s)
+        for (int k = 0; k < iext(L, s, 2); ++k)
+          for (int j = 0; j < iext(L, s, 1); ++j)
+            for (int i = 0; i < iext(L, s, 0); ++i) {
+              const Adj& v = O.at(s, i, j, k);
+              if (v.i >= 0) adj[v.i] += lam_out[8 * t + s][iidx(L, s, i, j, k)];
+            }
+      for (int32_t q = (int32_t)g_tape.a.size() - 1; q >= 0; --q) {
+        const double aq = adj[q];
+        if (aq == 0.0) continue;
+        if (g_tape.a[q] >= 0) adj[g_tape.a[q]] += aq * g_tape.da[q];
+        if (g_tape.b[q] >= 0) adj[g_tape.b[q]] += aq * g_tape.db[q];
+      }
+      for (int H = 0; H < ngrids; ++H)
+        for (int s = 0; s < NVAR; ++s) {
+          const std::vector<int32_t>& v = ids[(size_t)H * NVAR + s];
+          for (size_t e = 0; e < v.size(); ++e)
+            if (v[e] >= 0) lam_in[8 * H + s][e] += adj[v[e]];
+        }
+    }
+    g_tape.clear();
+    g_tape.a.shrink_to_fit();
+    g_tape.b.shrink_to_fit();
+    g_tape.da.shrink_to_fit();
+    g_tape.db.shrink_to_fit();
     return 0;
   } catch (const std::exception& e) {
     j_err = e.what();

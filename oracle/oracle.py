@@ -149,6 +149,23 @@ def hlld(L, R, gamma):
     return F, tuple(info)
 
 
+class hlld_paths:
+    """Context manager counting the oracle's HLLD paths inside it:
+    `with hlld_paths() as c: ...` then c.counts = (evaluations, outer star
+    degenerate, inner states evaluated, inner states degenerate)."""
+
+    def __enter__(self):
+        lib().orc_hlld_stats(C.c_int(1), None)
+        self.counts = None
+        return self
+
+    def __exit__(self, *exc):
+        out = (C.c_longlong * 4)()
+        lib().orc_hlld_stats(C.c_int(0), out)
+        self.counts = tuple(out)
+        return False
+
+
 # ------------------------------------------------------------------- runs
 def uniform_run(ic, gamma, cfl, nsteps, g=2, fill_every=1, bc=(0, 0, 0), dts=None):
     """Run a single uniform grid for nsteps.  Returns (fields[8], dts)."""
@@ -459,3 +476,35 @@ def step_vjp(ndim, n, gamma, dt, U, lam_out):
     if rc != 0:
         raise RuntimeError(_err())
     return ko
+
+
+def level_vjp(ndim, Nl, g, gamma, dx, dt, boxes, banded, sel, lam_out):
+    """(dM/dU)^T lam_out for M one substep of every grid of a level: the
+    same-level band copy (prolonged band elements held constant), then a
+    band-2 step of each grid (see orc_level_vjp).  boxes: per grid (lo, hi)
+    in level cells; banded: per grid 8 arrays in the banded layout (band g);
+    sel: grid indices whose output adjoint lam_out (per entry 8
+    interior-layout arrays) is given.  Returns per grid 8 interior-layout
+    arrays: the adjoint of the input on its own elements."""
+    L = lib()
+    L.orc_adj_last_error.restype = C.c_char_p
+    ng = len(boxes)
+    desc = np.zeros((ng, 6), dtype=np.int32)
+    for i, (lo, hi) in enumerate(boxes):
+        desc[i, :ndim] = lo[:ndim]
+        desc[i, 3:3 + ndim] = hi[:ndim]
+        desc[i, ndim:3] = 0
+        desc[i, 3 + ndim:] = 1
+    kb, pb = _ptrs([a for grid in banded for a in grid])
+    shapes = [interior_shapes(ndim, tuple(hi[a] - lo[a] for a in range(ndim))) for lo, hi in boxes]
+    kl, pl = _ptrs([np.asarray(a, dtype=np.float64).reshape(shapes[sel[t]][s])
+                    for t in range(len(sel)) for s, a in enumerate(lam_out[t])])
+    outs = [[np.zeros(sh) for sh in shapes[i]] for i in range(ng)]
+    ko, po = _ptrs([a for o in outs for a in o])
+    sl = np.ascontiguousarray(np.asarray(sel, dtype=np.int32))
+    rc = L.orc_level_vjp(C.c_int(ndim), _ivec(Nl), C.c_int(g), C.c_double(gamma), _dvec(dx), C.c_double(dt),
+                         C.c_int(ng), desc.ctypes.data_as(_ip), pb, C.c_int(len(sel)), sl.ctypes.data_as(_ip), pl,
+                         po)
+    if rc != 0:
+        raise RuntimeError("oracle level_vjp: " + L.orc_adj_last_error().decode())
+    return [ko[8 * i:8 * i + 8] for i in range(ng)]

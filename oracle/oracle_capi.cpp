@@ -196,6 +196,17 @@ void orc_hlld(const double* L, const double* R, double gamma, double* F, int* in
   }
 }
 
+// HLLD path counts since the last call (see HlldStats: evaluations, outer
+// star degenerate, inner states evaluated, inner states degenerate) into
+// out[4]; the counters restart from zero, counting only while `enable`.
+void orc_hlld_stats(int enable, long long* out) {
+  for (int k = 0; k < 4; ++k) {
+    if (out) out[k] = HlldStats::counts()[k].load();
+    HlldStats::counts()[k].store(0);
+  }
+  HlldStats::on() = enable != 0;
+}
+
 // Uniform single-grid run.  Band g; the band is refilled from the physical
 // boundary every `fill_every` steps (2*fill_every <= g).  dt of each step is
 // dts_in[s] if dts_in is given, else the CFL step of the current interior.

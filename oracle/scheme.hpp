@@ -19,6 +19,7 @@
 // on a reverse-mode tape (adjoint).  Branches compare primal values only, which
 // is exactly "branches frozen from the forward pass".
 #pragma once
+#include <atomic>
 #include <cmath>
 #include <utility>
 #include <cstddef>
@@ -77,6 +78,24 @@ template <class T> inline T Max(const T& a, const T& b) {
   BranchLog::note(value(b) > value(a));
   return value(b) > value(a) ? b : a;
 }
+
+// Path counts of the HLLD evaluations, for tests that must show which
+// branches a run reached (off unless enabled): [0] evaluations, [1] one side's
+// outer star state degenerate, [2] inner (double-star) states evaluated,
+// [3] inner states degenerate.
+struct HlldStats {
+  static bool& on() {
+    static bool v = false;
+    return v;
+  }
+  static std::atomic<long long>* counts() {
+    static std::atomic<long long> c[4];
+    return c;
+  }
+  static void add(int k) {
+    if (on()) counts()[k].fetch_add(1, std::memory_order_relaxed);
+  }
+};
 
 // Primitive slots (lab frame) and conserved slots share indices 0..7:
 //   W = (rho, vx, vy, vz, p, Bx, By, Bz),  U = (rho, mx, my, mz, E, Bx, By, Bz).
@@ -207,6 +226,7 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
   pflux(rR, uR, vR, wR, ptR, ER, byR, bzR, FR);
 
   HlldInfo inf;
+  HlldStats::add(0);
   BranchLog::note(10 + (value(SL) > 0.0));
   if (value(SL) > 0.0) {  // whole fan moves right: upwind flux is F_L
     for (int c = 0; c < 7; ++c) F[c] = FL[c];
@@ -251,6 +271,7 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
   Star sR = star(rR, uR, vR, wR, ptR, ER, byR, bzR, SR, dgR);
   inf.degen_star_L = dgL;
   inf.degen_star_R = dgR;
+  if (dgL || dgR) HlldStats::add(1);
 
   T sqL = Sqrt(sL.r), sqR = Sqrt(sR.r);
   T SLs = SM - Abs(Bn) / sqL;
@@ -301,6 +322,8 @@ inline void hlld(const T* L, const T* R, double gamma, T* F, HlldInfo* info = nu
   bool dd = 0.5 * value(Bn) * value(Bn) <= 1e-12 * value(pts);
   BranchLog::note(50 + dd);
   inf.degen_dstar = dd;
+  HlldStats::add(2);
+  if (dd) HlldStats::add(3);
   if (dd) {
     for (int c = 0; c < 7; ++c) { UssL[c] = UsL[c]; UssR[c] = UsR[c]; }
   } else {

@@ -191,6 +191,43 @@ def uniform_state(ndim, n, rho=1.0, v=(0.1, -0.05, 0.02), p=1.0, B=(0.3, 0.2, -0
     return {"prim": prim, "b": [bx, by, bz], "dx": dx, "ndim": ndim, "n": tuple(n)}
 
 
+def aligned_field_state(n, seed, B0=1.0, p0=0.1, eps=1e-7, amp=0.1):
+    """3D state that varies along y only: rho, p, vx, vy are sums of seeded
+    Fourier modes in y, vz = 0, and the face field is uniform, (B0, 0, eps)
+    with B0^2 well above gamma p.  Faces normal to x then see equal left and
+    right states with no transverse field and an Alfven-dominated fast speed
+    (the degenerate outer star states of HLLD), and faces normal to z see
+    equal states at rest with a vanishing normal field (degenerate inner
+    states)."""
+    n = tuple(int(v) for v in n)
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    y = (np.arange(ny) + 0.5) / ny
+
+    def modes():
+        f = np.zeros(ny)
+        for _ in range(4):
+            k = int(rng.integers(1, 5))
+            f += rng.uniform(0.5, 1.0) * np.cos(2.0 * np.pi * k * y + rng.uniform(0.0, 2.0 * np.pi))
+        return f / 4.0
+
+    shp = (nz, ny, nx)
+
+    def col(v):
+        return np.ascontiguousarray(np.broadcast_to(v[None, :, None], shp))
+
+    rho = col(1.0 + amp * modes())
+    p = col(p0 * (1.0 + amp * modes()))
+    vx = col(0.1 * modes())
+    vy = col(0.1 * modes())
+    vz = np.zeros(shp)
+    bx = np.full((nz, ny, nx + 1), float(B0))
+    by = np.zeros((nz, ny + 1, nx))
+    bz = np.full((nz + 1, ny, nx), float(eps))
+    return {"prim": [rho, vx, vy, vz, p], "b": [bx, by, bz], "dx": [1.0 / nx, 1.0 / ny, 1.0 / nz], "ndim": 3,
+            "n": n}
+
+
 def alfven_wave(ndim, N, amp=1e-6, gamma=5.0 / 3.0):
     """Linear Alfven wave on the unit box: B0 parallel to k, |B0| = 1, rho = 1,
     p = 1/gamma (so v_A = 1, omega = |k|); dB = amp e sin(k.x), dv = -dB.
