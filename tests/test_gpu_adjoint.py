@@ -141,7 +141,7 @@ def test_gpu_gradient_fp32_against_fp64_oracle():
     err = _relerr(g, go)
     log(f"adjoint FP32: J rel err {abs(J - Jo) / abs(Jo):.2e}, grad rel err vs FP64 oracle {err:.2e}")
     assert abs(J - Jo) <= 1e-5 * abs(Jo)
-    assert err <= 1e-4
+    assert err <= 1e-5
 
 
 def test_gpu_gradient_dot_tlm_64cubed():
