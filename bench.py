@@ -51,7 +51,7 @@ def kernel_source_digest():
     (the kernels and the host code that builds their work lists)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp", "runtime.hip"):
+    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp", "tables.hip"):
         with open(os.path.join(ROOT, "paper_1110_1616_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

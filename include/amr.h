@@ -376,6 +376,21 @@ amr_status amr_get_error_flags(amr_hierarchy* h, uint32_t* flags, int64_t* first
  * forward-mode dual number.  `which` out of range or ntrials < 1 returns -1. */
 double amr_selfcheck_adjoint(int32_t which, int32_t ntrials, uint64_t seed);
 
+/* Host-only check of the advance kernels' addressing (no GPU needed): builds
+ * the hierarchy's tables as amr_validate() does and, for every work list and
+ * an element size of elem_bytes (4, 8 or 16), walks the work items as the
+ * flux and update kernels do, checking that each 32-bit byte offset the
+ * flux kernel loads or stores equals the 64-bit element offset times the
+ * element size, that every access lies in its grid's padded box, that no
+ * face flux has two writers in one launch, and that every face flux the
+ * update reads (directly or through an edge EMF) was written in the same
+ * launch.  stats (may be NULL, else 3 entries): loads, stores and reads
+ * checked.  AMR_EINVAL with the first failure in amr_last_error();
+ * AMR_EUNSUPPORTED when a field array of that element size would exceed
+ * 4 GiB. */
+amr_status amr_selfcheck_addressing(const amr_params* p, const amr_grid* grids, int32_t ngrids, int32_t elem_bytes,
+                                    int64_t* stats);
+
 /* ---- predictive balancing of launch cycles ----
  * One coarse step runs R^(L-1) launch cycles.  Step k of a level-l grid has
  * a window of W = R^(L-1-l) cycles, [k W, (k+1) W): its band is filled at the

@@ -80,6 +80,8 @@ def lib():
                                               _VP]
         L.amr_advance_patches.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                           C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP, _VP]
+        L.amr_selfcheck_addressing.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.c_int32,
+                                               C.POINTER(C.c_int64)]
         L.amr_coarse_step.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.POINTER(C.c_uint32), _VP,
                                       _VP, C.c_int32, _VP]
         L.amr_restrict_fluxfix.argtypes = [_VP, C.c_int32, C.POINTER(amr_state), C.POINTER(amr_state), _VP, _VP]
@@ -158,6 +160,16 @@ def amr_validate(params, grids):
     keys = ("grids", "state_elems", "workspace_bytes", "copy_entries", "prolong_entries", "sync_entries",
             "flux_items", "update_items")
     return dict(zip(keys, list(st)))
+
+
+def amr_selfcheck_addressing(params, grids, elem_bytes):
+    """Host-only check of the advance kernels' addressing for element size
+    elem_bytes (4, 8 or 16); returns (loads, stores, reads) checked."""
+    arr = (amr_grid * len(grids))(*grids)
+    st = (C.c_int64 * 3)()
+    _check(lib().amr_selfcheck_addressing(C.byref(params), arr, len(grids), int(elem_bytes), st),
+           "amr_selfcheck_addressing")
+    return tuple(st)
 
 
 def make_params(ndim, domain, nlevels=1, ratio=2, ghost=2, dtype="f64", bc=(0, 0, 0), dx0=None, gamma=5.0 / 3.0,

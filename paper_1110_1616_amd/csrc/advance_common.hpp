@@ -9,12 +9,12 @@ namespace amr {
 template <int NDIM> struct Idx {
   int64_t base;  // element of cell (0,0,0)
   int32_t sy, sz;
-  __device__ __forceinline__ Idx(const GridDesc& G) {
+  __host__ __device__ __forceinline__ Idx(const GridDesc& G) {
     sy = G.P[0];
     sz = G.P[0] * G.P[1];
     base = G.off + G.g + (int64_t)G.g * sy + (NDIM == 3 ? (int64_t)G.g * sz : 0);
   }
-  __device__ __forceinline__ int64_t operator()(int i, int j, int k) const {
+  __host__ __device__ __forceinline__ int64_t operator()(int i, int j, int k) const {
     return base + i + (int64_t)j * sy + (NDIM == 3 ? (int64_t)k * sz : 0);
   }
 };
@@ -29,13 +29,13 @@ template <int NDIM, class T> struct IdxB {
   using B = typename ByteOffset<T>::type;
   B b0;            // cell (0,0,0)
   int32_t sy, sz;  // row and plane strides
-  __device__ __forceinline__ IdxB(const GridDesc& G) {
+  __host__ __device__ __forceinline__ IdxB(const GridDesc& G) {
     sy = G.P[0] * (int32_t)sizeof(T);
     sz = G.P[0] * G.P[1] * (int32_t)sizeof(T);
     const int64_t e0 = G.off + G.g + (int64_t)G.g * G.P[0] + (NDIM == 3 ? (int64_t)G.g * G.P[0] * G.P[1] : 0);
     b0 = (B)(e0 * (int64_t)sizeof(T));
   }
-  __device__ __forceinline__ B operator()(int i, int j, int k) const {
+  __host__ __device__ __forceinline__ B operator()(int i, int j, int k) const {
     return b0 + (B)(i * (int32_t)sizeof(T) + j * sy + (NDIM == 3 ? k * sz : 0));
   }
 };

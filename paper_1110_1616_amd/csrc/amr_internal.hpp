@@ -73,8 +73,9 @@ template <class T> struct DevFlux {
 // Element load / store at a 32-bit byte offset b from a base pointer that is
 // uniform over the work item: the scalar-base address form, one 32-bit lane
 // register per access instead of a 64-bit address.
-// The offset type: 32-bit for the arithmetic types; the frozen-branch pair
-// types (finite-difference verification only) specialise it to 64-bit.
+// The offset type: 32-bit for the arithmetic types (a hierarchy's set-up
+// bounds each field array below 4 GiB; amr_selfcheck_addressing() checks the
+// offsets on the host); the frozen-branch pair types specialise it to 64-bit.
 template <class T> struct ByteOffset { using type = uint32_t; };
 
 template <class T, class B> __device__ __forceinline__ T ldb(const T* p, B b) {

@@ -39,7 +39,14 @@ template <> __host__ __device__ __forceinline__ Frozen<float> dsqrt<Frozen<float
   return Frozen<float>(__builtin_sqrtf(x.b), __builtin_sqrtf(x.p), 0);
 }
 
-// 64-bit byte offsets for the pair types in the advance kernels' addressing
+// 64-bit byte offsets for the pair types in the flux kernel's addressing.
+// The 32-bit offsets of the arithmetic types are exact for 16-byte elements
+// too (amr_selfcheck_addressing walks every work list with that element
+// size), yet the pair-type flux kernel compiled with them produced results
+// that read unwritten workspace on the GPU; the cause lies outside the
+// offset arithmetic and was not found, so the pair types keep 64-bit
+// offsets (finite-difference verification only; they take no part in the
+// timed path).
 template <class S> struct ByteOffset<Frozen<S>> { using type = uint64_t; };
 
 using FrozenD = Frozen<double>;

@@ -118,3 +118,48 @@ def test_validate_refuses_fields_over_4gib():
     p = A.make_params(3, (n, n, n), nlevels=1, ghost=4)
     with pytest.raises(A.AmrError, match="4 GiB"):
         A.amr_validate(p, A.make_grids([(0, (0, 0, 0), (n, n, n))]))
+
+
+ADDR_CASES = [
+    ("64^3 g=2", 3, (64, 64, 64), [(0, (0, 0, 0), (64, 64, 64))], 1, 2, 0),
+    ("4 tiles g=4", 3, (16, 16, 16), [(0, (0, 0, 0), (8, 8, 16)), (0, (8, 0, 0), (16, 8, 16)),
+                                      (0, (0, 8, 0), (8, 16, 16)), (0, (8, 8, 0), (16, 16, 16))], 1, 4, 0),
+    ("2D 2 tiles", 2, (40, 32), [(0, (0, 0), (18, 32)), (0, (18, 0), (40, 32))], 1, 4, 0),
+    ("2-level upwind", 3, (16, 16, 16), None, 2, 4, 1),
+]
+
+
+@pytest.mark.parametrize("elem_bytes", [4, 8, 16])
+@pytest.mark.parametrize("case", ADDR_CASES, ids=[c[0] for c in ADDR_CASES])
+def test_flux_kernel_addressing_host_check(case, elem_bytes):
+    """Every 32-bit byte offset the flux kernel forms equals the 64-bit
+    element offset times the element size, stays in its grid's box; each
+    face flux has one writer per launch and every flux the update kernel
+    reads was written in the same launch (all work lists)."""
+    from paper_1110_1616_amd import inputs as I
+    name, ndim, N, grids, nlev, g, emf = case
+    if grids is None:
+        grids = I.amr_hierarchy(3, N, 2, seed=11, ext=(8, 16))
+    p = A.make_params(ndim, N, nlevels=nlev, ghost=g, emf=emf)
+    loads, stores, reads = A.amr_selfcheck_addressing(p, A.make_grids(grids), elem_bytes)
+    assert loads > 0 and stores > 0 and (reads > 0 or emf)
+
+
+@pytest.mark.slow
+def test_flux_kernel_addressing_benchmark_hierarchy():
+    """The same check on the 3-level benchmark hierarchy (549 grids) for
+    FP64 and for 16-byte elements."""
+    from paper_1110_1616_amd import inputs as I
+    grids = I.amr_hierarchy(3, (112, 112, 112), 3, seed=3, ext=(8, 32))
+    p = A.make_params(3, (112, 112, 112), nlevels=3, ghost=4)
+    for eb in (8, 16):
+        loads, stores, reads = A.amr_selfcheck_addressing(p, A.make_grids(grids), eb)
+        assert stores > 1e8 and reads > 1e9
+
+
+def test_addressing_check_rejects_bad_element_sizes():
+    p = A.make_params(3, (16, 16, 16), nlevels=1, ghost=2)
+    grids = A.make_grids([(0, (0, 0, 0), (16, 16, 16))])
+    for eb in (0, 2, 12, 32):
+        with pytest.raises(A.AmrError):
+            A.amr_selfcheck_addressing(p, grids, eb)
