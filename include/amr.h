@@ -205,6 +205,25 @@ amr_status amr_advance_patches(amr_hierarchy* h, int32_t cycle, const int32_t* g
                                int32_t band, const amr_state* U_a, const amr_state* U_b, uint32_t parity,
                                const double* dt0, void* workspace, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * amr_advance_patches() with the same arguments and results (bit for bit),
+ * but without the workspace argument.  The flux arrays and coarse/fine
+ * registers live in a static device array of the library, 256 MiB per
+ * device, held from the first amr_create() on that device until the process
+ * ends; the call allocates nothing.  AMR_EINVAL (with the sizes in
+ * amr_last_error()) when the hierarchy's workspace (amr_layout) exceeds
+ * 256 MiB, or when the current device is not the one the hierarchy was
+ * created on.  All calls on one device share the array: calls that overlap
+ * on a device (two streams, two host threads) race, and the registers it
+ * writes are overwritten by the next call (a caller that synchronises
+ * levels with amr_restrict_fluxfix() uses amr_advance_patches()).  Nothing
+ * in the array needs to start at zero: each call writes every element it
+ * reads.  Kernel timing (amr_set_kernel_timing) is off for this call. */
+amr_status amr_advance_patches_noalloc(amr_hierarchy* h, int32_t cycle, const int32_t* grid_subset,
+                                       int32_t nsubset, int32_t band, const amr_state* U_a, const amr_state* U_b,
+                                       uint32_t parity, const double* dt0, void* stream);
+
 /* Synchronise level fine_level-1 with fine_level after the fine level's R
  * substeps (the (S)ynchronise and (R)estrict of Sec. 4), from the registers
  * in workspace: (1) reflux: each uncovered coarse cell next to covered ones

@@ -80,6 +80,8 @@ def lib():
                                               _VP]
         L.amr_advance_patches.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                                           C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP, _VP]
+        L.amr_advance_patches_noalloc.argtypes = [_VP, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                                  C.POINTER(amr_state), C.POINTER(amr_state), C.c_uint32, _VP, _VP]
         L.amr_selfcheck_addressing.argtypes = [C.POINTER(amr_params), C.POINTER(amr_grid), C.c_int32, C.c_int32,
                                                C.POINTER(C.c_int64)]
         L.amr_coarse_step.argtypes = [_VP, C.POINTER(amr_state), C.POINTER(amr_state), C.POINTER(C.c_uint32), _VP,
@@ -236,6 +238,16 @@ def amr_advance_patches(h, cycle, subset, band, Ua, Ub, parity, dt0, ws):
         arr, n = None, 0
     _check(lib().amr_advance_patches(h, cycle, arr, n, band, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0), _ptr(ws),
                                      _stream()), "amr_advance_patches")
+
+
+def amr_advance_patches_noalloc(h, cycle, subset, band, Ua, Ub, parity, dt0):
+    if subset:
+        arr = (C.c_int32 * len(subset))(*subset)
+        n = len(subset)
+    else:
+        arr, n = None, 0
+    _check(lib().amr_advance_patches_noalloc(h, cycle, arr, n, band, C.byref(Ua), C.byref(Ub), parity, _ptr(dt0),
+                                             _stream()), "amr_advance_patches_noalloc")
 
 
 def amr_coarse_step(h, Ua, Ub, parity, dt0, ws, mode=0):

@@ -283,6 +283,8 @@ amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids
         kernel_occupancy<float>(h->ndim, &fb, &ub);
       h->flux_pblocks = prop.multiProcessorCount * fb;
       h->upd_pblocks = prop.multiProcessorCount * ub;
+      h->device = dev;
+      scratch_init_device(dev);
     }
     HIPCHK(hipDeviceSynchronize());
     *out = h;

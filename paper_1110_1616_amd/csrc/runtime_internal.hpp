@@ -152,6 +152,7 @@ struct amr_hierarchy {
   bool xcd_chunks = false;     // item lists cut into one contiguous chunk per XCD
   WorkQueue* d_queue = nullptr;
   int flux_pblocks = 0, upd_pblocks = 0;  // persistent grid sizes (resident blocks on the device)
+  int device = 0;  // the device the tables live on (current at amr_create)
 
   // captured coarse steps: graph[p] starts from level-0 parity bit p
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -371,5 +372,8 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
 void advance_patches(amr_hierarchy* h, int32_t cycle, const int32_t* grid_subset, int32_t nsubset, int32_t band,
                      const amr_state* U_a, const amr_state* U_b, uint32_t parity, const double* dt0, void* workspace,
                      hipStream_t s);
+// Resolve, once per device, the device address of the allocation-free
+// entry point's static scratch array on the current device (noalloc.hip).
+void scratch_init_device(int device);
 
 }  // namespace amrrt
