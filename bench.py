@@ -196,6 +196,10 @@ def amr_workload(args, deep=False):
         with torch.cuda.stream(stream):
             H.graph_capture(Ua, Ub, st["par"], 0)
 
+    def capture_per_grid():
+        with torch.cuda.stream(stream):
+            H.graph_capture(Ua, Ub, st["par"], 1)
+
     def graph_step():
         with torch.cuda.stream(stream):
             st["par"] = H.graph_launch(st["par"])
@@ -289,7 +293,7 @@ def amr_workload(args, deep=False):
                 "cell_updates_per_s_after": sum(c * 2 ** l for l, c in enumerate(c2)) / (e0.elapsed_time(e1) / 3e3)}
 
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
-            "per_grid": eager(1), "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
+            "per_grid": eager(1), "prepare_per_grid": capture_per_grid, "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
             "tune": tune, "regrid": None if deep else regrid_measure, "schedules": True}
 
 
@@ -493,11 +497,20 @@ def main():
     flux_ms, upd_ms, nl = A.amr_kernel_times(H.h)
     A.amr_set_kernel_timing(H.h, False)
 
-    per_grid = None
+    per_grid = per_grid_graph = None
     if W["per_grid"] is not None and args.per_grid_steps > 0:
         progress("timing the per-grid path")
         pg_ms = timed(W["per_grid"], args.per_grid_steps)
         per_grid = float(info["cells"]) * args.per_grid_steps / (pg_ms / 1e3)
+        if W.get("prepare_per_grid"):
+            # the same serial per-grid order replayed from a captured graph
+            # (no host launch overhead); replaces the batched graphs
+            progress("capturing and timing the per-grid path as a HIP graph")
+            W["prepare_per_grid"]()
+            torch.cuda.synchronize()
+            W["step"]()
+            pgg_ms = timed(W["step"], args.per_grid_steps)
+            per_grid_graph = float(info["cells"]) * args.per_grid_steps / (pgg_ms / 1e3)
 
     flags, _ = H.error_flags()
     if flags:
@@ -539,6 +552,9 @@ def main():
     if per_grid is not None:
         out["per_grid_value"] = per_grid
         out["batched_over_per_grid"] = value / per_grid
+    if per_grid_graph is not None:
+        out["per_grid_graph_value"] = per_grid_graph
+        out["batched_over_per_grid_graph"] = value / per_grid_graph
     if tuned is not None:
         out["autotune"] = tuned
     if sched is not None:

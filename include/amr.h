@@ -336,9 +336,16 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * (workgroups reach the XCDs round-robin, so chunk c runs on XCD c and
  * neighbouring tiles share its L2; persistent blocks drain their own chunk
  * first, then the others); bit 2: persistent launches of the flux kernel
- * only, the update one block per item (implied for the flux kernel by bit 0;
- * launch_mode in [0, 7], else AMR_EINVAL).  Results do not depend on the
- * configuration (bitwise).  Changing tile_policy or zchunk rebuilds the work
+ * only, the update one block per item (implied for the flux kernel by bit 0);
+ * bit 3: one fused flux-update kernel per launch instead of the two (tiles
+ * overlapping by two cells, face fluxes kept in LDS; only those the
+ * coarse/fine registers read are stored; persistent with bit 0 or 2; the
+ * upwinded EMF always takes the two-kernel path).  launch_mode in [0, 15],
+ * else AMR_EINVAL.  The two-kernel configurations give bitwise identical
+ * results, and so do the fused ones of one tile policy; in FP64 the fused
+ * kernel differs from the two-kernel path, and between tile policies, by an
+ * ulp here and there (the same expressions, compiled with different
+ * multiply-add contraction; FP32 results agree bit for bit).  Changing tile_policy or zchunk rebuilds the work
  * lists and drops captured graphs.  Default: 1, 16, 0. */
 amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
@@ -352,7 +359,7 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
 amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk);
 amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk);
 
-#define AMR_TUNE_CANDIDATES 52
+#define AMR_TUNE_CANDIDATES 84
 
 typedef struct {
   int32_t tile_policy, zchunk, launch_mode, update_zchunk;
@@ -361,12 +368,12 @@ typedef struct {
 
 /* Autotuner of the batched advance: fills every level's band (FULL, coarse
  * to fine) and computes dt0 (both redone by the next coarse step), then
- * times the 48 configurations tile_policy x zchunk in {8, 12, 16, 32} x
- * launch_mode in {0, 1, 2, 3, 4, 6} (entries 0..47, under the current update
- * z-chunk), keeps the fastest, and under it times the update z-chunks
- * {1, 2, 4, 8} (entries 48..51), each over `reps` passes of every launch
- * cycle's batched advance, reading each level's current buffer (parity) and
- * writing the other one, and keeps the fastest of all 52.  The state the
+ * times the 80 configurations tile_policy x zchunk in {8, 12, 16, 32} x
+ * launch_mode in {0, 1, 2, 3, 4, 6, 8, 10, 12, 14} (entries 0..79, under the
+ * current update z-chunk), keeps the fastest, and under it times the update
+ * z-chunks {1, 2, 4, 8} (entries 80..83), each over `reps` passes of every
+ * launch cycle's batched advance, reading each level's current buffer
+ * (parity) and writing the other one, and keeps the fastest of all 84.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamrmhd.so")
 ROOT = os.path.dirname(HERE)
-SOURCES = ["runtime.hip", "tables.hip", "autotune.hip", "adjoint_driver.hip", "regrid_driver.hip", "noalloc.hip", "addrcheck.hip", "advance.hip", "fill.hip", "sync.hip", "adjoint.hip", "frozen.hip", "selfcheck.hip", "regrid.hip"]
+SOURCES = ["runtime.hip", "tables.hip", "autotune.hip", "adjoint_driver.hip", "regrid_driver.hip", "noalloc.hip", "addrcheck.hip", "advance.hip", "fused.hip", "fill.hip", "sync.hip", "adjoint.hip", "frozen.hip", "selfcheck.hip", "regrid.hip"]
 ARCH = "gfx950"
 
 

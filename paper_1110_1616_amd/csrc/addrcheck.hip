@@ -205,7 +205,184 @@ template <int NDIM, class T> struct Walker {
     }
   }
 
+  // ---- the fused flux-update kernel (see fused.hip), same predicates ----
+  // counts of updates per element (cells, B_x, B_y, B_z) and of flux stores
+  std::vector<uint8_t>* up;      // [4]
+  std::vector<int64_t>* utouch;  // [4]
+  static bool owns(int t, int tdim, int c, int clo, int chi) {
+    return (t >= 1 && t <= tdim - 2) || (t == 0 && c == clo) || (t == tdim - 1 && c == chi);
+  }
+  void upd(int which, int64_t e, const FluxItem& it) {
+    uint8_t& w = up[which][e];
+    if (w) bad("fused: element updated twice in one launch (field class " + std::to_string(which) + ")", &it, e);
+    w = 1;
+    utouch[which].push_back(e);
+    ++cnt->reads;
+  }
+  void fused_item(const FluxItem& it) {
+    const GridDesc& G = h->desc[it.grid];
+    const Idx<NDIM> ix(G);
+    const IdxB<NDIM, T> bx(G);
+    const int gv = it.gv, cl = -gv + 1;
+    const int chx = G.n[0] + gv - 1, chy = G.n[1] + gv - 1;
+    const int wlo = -gv, whix = G.n[0] + gv, whiy = G.n[1] + gv;
+    const int ul = -gv + 2;
+    const int uhx = G.n[0] + gv - 2, uhy = G.n[1] + gv - 2, uhz = NDIM == 3 ? G.n[2] + gv - 2 : 1;
+    const int tw = it.tw, th = 256 / tw;
+    const int z0 = NDIM == 3 ? it.z0 : 0, z1 = NDIM == 3 ? it.z1 : 1;
+    const int kstart = NDIM == 3 ? z0 - 1 : 0, kend = NDIM == 3 ? std::min(z1, uhz) : 0;
+    const uint8_t* mask = h->h_fmask.empty() ? nullptr : h->h_fmask.data();
+    auto lane = [&](int t, int& cx, int& cy, bool& live, bool& act, bool& xf, bool& yf) {
+      const int tx = t % tw, ty = t / tw;
+      live = ty < th;
+      cx = it.x0 - 1 + tx;
+      cy = it.y0 - 1 + ty;
+      act = live && cx >= cl && cx < chx && cy >= cl && cy < chy;
+      xf = act && tx >= 1 && cx > cl;
+      yf = act && ty >= 1 && cy > cl;
+    };
+    auto need = [&](bool c, const char* what, int64_t e) {
+      if (!c) bad(std::string("fused: ") + what, &it, e);
+    };
+    for (int tid = 0; tid < 256; ++tid) {
+      const int tx = tid % tw, ty = tid / tw;
+      int cx, cy;
+      bool live, act, xf, yf;
+      lane(tid, cx, cy, live, act, xf, yf);
+      const bool ucol = tx >= 1 && tx <= tw - 2 && cx >= ul && cx < uhx;
+      const bool urow = ty >= 1 && ty <= th - 2 && cy >= ul && cy < uhy;
+      const bool ucell = live && ucol && urow;
+      const bool ubx = live && urow && (ucol || (tx >= 1 && cx == uhx));
+      const bool uby = live && ucol && (urow || (ty >= 1 && cy == uhy));
+      const bool sx = owns(tx, tw, cx, cl, chx - 1), sy = owns(ty, th, cy, cl, chy - 1);
+      const bool rok_dummy = false;
+      (void)rok_dummy;
+      // neighbour lanes
+      auto nb = [&](int t, bool& nact, bool& nxf, bool& nyf) {
+        int a, b;
+        bool l;
+        lane(t, a, b, l, nact, nxf, nyf);
+      };
+      bool l_act, l_xf, l_yf, d_act, d_xf, d_yf, r_act, r_xf, r_yf, u_act, u_xf, u_yf;
+      l_act = l_xf = l_yf = d_act = d_xf = d_yf = r_act = r_xf = r_yf = u_act = u_xf = u_yf = false;
+      if (tx >= 1) nb(tid - 1, l_act, l_xf, l_yf);
+      if (ty >= 1) nb(tid - tw, d_act, d_xf, d_yf);
+      if (tx + 1 < tw) nb(tid + 1, r_act, r_xf, r_yf);
+      if (ty + 1 < th && tid + tw < 256) nb(tid + tw, u_act, u_xf, u_yf);
+      const bool ook = live && cx >= wlo && cx < whix && cy >= wlo && cy < whiy;
+      if (ook) {
+        if (NDIM == 3) load_cell(G, bx, ix, cx, cy, kstart - 1, it);
+        for (int k = kstart; k <= kend + (NDIM == 3 ? 1 : 0); ++k) load_cell(G, bx, ix, cx, cy, k, it);
+      }
+      const bool ez = xf && yf;
+      if (ez) need(d_xf && l_yf, "E_z reads a face its neighbour lane did not solve", ix(cx, cy, 0));
+      for (int k = kstart; k <= kend; ++k) {
+        const int64_t e = ix(cx, cy, k);
+        const bool zf = NDIM == 3 && act && k >= z0;
+        if (act && mask && (mask[e] & 7u)) {
+          const bool plane_ok = NDIM == 2 || (k >= z0 && k < z1) || (k == kstart && z0 == ul);
+          if (xf && (mask[e] & 1u) && sx && sy && plane_ok) store(0, G, bx, ix, cx, cy, k, it);
+          if (yf && (mask[e] & 2u) && sx && sy && plane_ok) store(1, G, bx, ix, cx, cy, k, it);
+          if (zf && (mask[e] & 4u) && sx && sy && k < z1) store(2, G, bx, ix, cx, cy, k, it);
+        }
+        const bool exv = NDIM == 3 && k >= z0 && yf, eyv = NDIM == 3 && k >= z0 && xf;
+        if (exv) need(d_act, "E_x reads a z-face its neighbour lane did not solve", e);
+        if (eyv) need(l_act, "E_y reads a z-face its neighbour lane did not solve", e);
+        if (NDIM == 3) {
+          if (ucell && k >= z0 && k < z1) {
+            need(eyv && exv && r_xf && u_yf, "B_z face update reads an EMF that was not formed", e);
+            upd(3, e, it);
+          }
+          const int kk = k - 1;
+          if (kk >= z0 && kk < z1 && kk < uhz) {
+            const int64_t ec = ix(cx, cy, kk);
+            if (ucell) {
+              need(xf && r_xf && yf && u_yf && zf, "cell update reads a flux that was not formed", ec);
+              upd(0, ec, it);
+            }
+            if (ubx) {
+              need(ez && u_xf && u_yf && eyv && kk >= z0, "B_x update reads an EMF that was not formed", ec);
+              upd(1, ec, it);
+            }
+            if (uby) {
+              need(ez && r_xf && r_yf && exv && kk >= z0, "B_y update reads an EMF that was not formed", ec);
+              upd(2, ec, it);
+            }
+          }
+        } else {
+          if (ucell) {
+            need(xf && r_xf && yf && u_yf, "cell update reads a flux that was not formed", e);
+            upd(0, e, it);
+          }
+          if (ubx) {
+            need(ez && u_xf && u_yf, "B_x update reads an EMF that was not formed", e);
+            upd(1, e, it);
+          }
+          if (uby) {
+            need(ez && r_xf && r_yf, "B_y update reads an EMF that was not formed", e);
+            upd(2, e, it);
+          }
+        }
+      }
+    }
+  }
+  // every update-region element of every grid step in the list updated once
+  // and every face flux a register reads stored once
+  void fused_coverage(const LaunchList& L) {
+    std::vector<std::pair<int, int>> steps;
+    for (int i = 0; i < L.fused.n; ++i) {
+      const FluxItem& it = h->h_xitems[L.fused.off + i];
+      if (steps.empty() || steps.back() != std::make_pair(it.grid, it.gv)) steps.push_back({it.grid, it.gv});
+    }
+    const uint8_t* mask = h->h_fmask.empty() ? nullptr : h->h_fmask.data();
+    for (auto gs : steps) {
+      const GridDesc& G = h->desc[gs.first];
+      const Idx<NDIM> ix(G);
+      const int gv = gs.second, ul = -gv + 2, cl = -gv + 1;
+      const int uh[3] = {G.n[0] + gv - 2, G.n[1] + gv - 2, NDIM == 3 ? G.n[2] + gv - 2 : 1};
+      const int zl = NDIM == 3 ? ul : 0;
+      FluxItem f{};
+      f.grid = gs.first;
+      f.gv = gv;
+      for (int k = zl; k <= uh[2]; ++k)
+        for (int j = ul; j <= uh[1]; ++j)
+          for (int i = ul; i <= uh[0]; ++i) {
+            const int64_t e = ix(i, j, k);
+            const bool ci = i < uh[0], cj = j < uh[1], ck = NDIM == 2 || k < uh[2];
+            if (ci && cj && ck && !up[0][e]) bad("fused: cell not updated", &f, e);
+            if (cj && ck && !up[1][e]) bad("fused: B_x face not updated", &f, e);
+            if (ci && ck && !up[2][e]) bad("fused: B_y face not updated", &f, e);
+            if (NDIM == 3 && ci && cj && !up[3][e]) bad("fused: B_z face not updated", &f, e);
+          }
+      if (!mask) continue;
+      // register faces of this grid's step: within the computed face region
+      const int ch[3] = {G.n[0] + gv - 1, G.n[1] + gv - 1, NDIM == 3 ? G.n[2] + gv - 1 : 1};
+      const int zc0 = NDIM == 3 ? cl : 0;
+      for (int k = zc0; k < ch[2]; ++k)
+        for (int j = cl; j < ch[1]; ++j)
+          for (int i = cl; i < ch[0]; ++i) {
+            const int64_t e = ix(i, j, k);
+            for (int d = 0; d < NDIM; ++d)
+              if ((mask[e] >> d) & 1u) {
+                const int c[3] = {i, j, k};
+                if (c[d] == cl) continue;  // no face below the computed region
+                if (!wr[d][e]) bad("fused: a register's face flux was not stored (direction " + std::to_string(d) + ")", &f, e);
+              }
+          }
+    }
+  }
+
   void list(const LaunchList& L) {
+    if (!h->upwind_emf && L.fused.n > 0) {
+      for (int i = 0; i < L.fused.n; ++i) fused_item(h->h_xitems[L.fused.off + i]);
+      fused_coverage(L);
+      for (int d = 0; d < 4; ++d) {
+        for (int64_t e : touched[d]) wr[d][e] = 0;
+        touched[d].clear();
+        for (int64_t e : utouch[d]) up[d][e] = 0;
+        utouch[d].clear();
+      }
+    }
     for (int i = 0; i < L.flux.n; ++i) flux_item(h->h_fitems[L.flux.off + i]);
     for (int i = 0; i < L.upd.n; ++i) update_item(h->h_uitems[L.upd.off + i]);
     for (int d = 0; d < 4; ++d) {
@@ -216,10 +393,11 @@ template <int NDIM, class T> struct Walker {
 };
 
 template <int NDIM, class T> void check_all(const amr_hierarchy* h, Counts& cnt) {
-  std::vector<uint8_t> wr[4];
-  std::vector<int64_t> touched[4];
+  std::vector<uint8_t> wr[4], up[4];
+  std::vector<int64_t> touched[4], utouch[4];
   for (auto& w : wr) w.assign(h->total_elems, 0);
-  Walker<NDIM, T> W{h, &cnt, wr, touched};
+  for (auto& w : up) w.assign(h->total_elems, 0);
+  Walker<NDIM, T> W{h, &cnt, wr, touched, up, utouch};
   for (const LaunchList& L : h->cycle_lists) W.list(L);
   for (const LaunchList& L : h->eta_lists) W.list(L);
   for (const LaunchList& L : h->band2_lists) W.list(L);

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "advance_common.hpp"
+#include "launch_common.hpp"
 #include "amr_internal.hpp"
 #include "emf.hpp"
 #include "frozen.hpp"
@@ -22,87 +23,6 @@
 namespace amr {
 
 namespace {
-
-// A flux tile is tw x th threads (tw in [kMinTile, kMaxTile], th = 256 / tw)
-// over cells (x0-1+tx, y0-1+ty); the LDS plane adds one ring cell on each
-// side: (tw+2) x (th+2) entries, at most kMaxPlane.
-constexpr int kMaxPlane = 396;  // max over tw in [4, 64] of (tw + 2)(256 / tw + 2)
-
-// Ring entry r in [0, 2 (tw + th)) of the plane -> (ex, ey): the one-cell
-// border of the tile's (tw + 2) x (th + 2) LDS plane without its four
-// corners, which no cell reads (the slopes use the x and y neighbours only).
-// A 16 x 16 tile's 64 ring cells are then one wave's lanes.
-__device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& ey) {
-  if (r < tw) { ex = r + 1; ey = 0; }
-  else if (r < 2 * tw) { ex = r - tw + 1; ey = th + 1; }
-  else if (r < 2 * tw + th) { ex = 0; ey = r - 2 * tw + 1; }
-  else { ex = tw + 1; ey = r - 2 * tw - th + 1; }
-}
-
-// Next work item of this block.  Grid-stride launches take blockIdx.x,
-// blockIdx.x + gridDim.x, ...; persistent launches (a fixed number of blocks)
-// pop the shared queue, one atomic per item, in list order (finest level
-// first), so blocks that draw cheap items come back for more.  With `xcd`
-// the list is cut into 8 contiguous chunks, one per XCD (workgroups are
-// dispatched to the 8 XCDs round-robin, so block b runs on XCD b mod 8):
-// neighbouring tiles, which share halo data, then run under one L2.  A
-// one-block-per-item launch maps block b to item (b mod 8) C + b / 8; a
-// persistent block pops its own chunk first, then the others.  Returns -1
-// when the list is exhausted.
-template <bool PERSIST>
-__device__ __forceinline__ int next_item(int& cursor, int nitems, WorkQueue* q, int* s_it, int* s_c, bool xcd) {
-  const int C = (nitems + 7) >> 3;
-  if (!PERSIST) {
-    if (xcd) {
-      if (cursor < 0) return -1;
-      const int b = cursor;
-      cursor = -1;
-      const int it = (b & 7) * C + (b >> 3);
-      return it < nitems ? it : -1;
-    }
-    const int it = cursor;
-    cursor += gridDim.x;
-    return it < nitems ? it : -1;
-  }
-  if (threadIdx.x == 0) {
-    int res = -1;
-    if (!xcd) {
-      const unsigned i = atomicAdd(&q->head[0], 1u);
-      if ((int)i < nitems) res = (int)i;
-    } else {
-      while (res < 0 && *s_c < 8) {
-        const int c = (int)((blockIdx.x + *s_c) & 7);
-        const int lo = c * C, len = min(C, nitems - lo);
-        if (len > 0) {
-          const unsigned i = atomicAdd(&q->head[c], 1u);
-          if ((int)i < len) res = lo + (int)i;
-        }
-        if (res < 0) ++*s_c;  // this chunk is drained: move to the next
-      }
-    }
-    *s_it = res;
-  }
-  __syncthreads();
-  const int it = *s_it;
-  __syncthreads();
-  return it;
-}
-
-// Persistent launches leave the queue ready for the next one: the last block
-// to finish resets the counters (every other block has made its final pop
-// before it counts itself done).
-template <bool PERSIST>
-__device__ __forceinline__ void retire(WorkQueue* q) {
-  if (!PERSIST) return;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned d = atomicAdd(&q->done, 1u);
-    if (d == gridDim.x - 1) {
-      for (int c = 0; c < 8; ++c) atomicExch(&q->head[c], 0u);
-      atomicExch(&q->done, 0u);
-    }
-  }
-}
 
 template <class T, int NDIM, bool PERSIST, bool UPWIND>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
@@ -345,21 +265,17 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
         // lab conserved slot -> rotated component of direction d
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-          T acc;
-          if (s == 0 || s == 4) {
-            acc = cdx * (F.f[0][s][e + 1] - F.f[0][s][e]) + cdy * (F.f[1][s][e + st[1]] - F.f[1][s][e]);
-            if (NDIM == 3) acc += cdz * (F.f[2][s][e + st[2]] - F.f[2][s][e]);
-          } else {
-            const int a = s - 1;
-            const int qx = 1 + (a + 3 - 0) % 3, qy = 1 + (a + 3 - 1) % 3, qz = 1 + (a + 3 - 2) % 3;
-            acc = cdx * (F.f[0][qx][e + 1] - F.f[0][qx][e]) + cdy * (F.f[1][qy][e + st[1]] - F.f[1][qy][e]);
-            if (NDIM == 3) acc += cdz * (F.f[2][qz][e + st[2]] - F.f[2][qz][e]);
-          }
+          // lab conserved slot s -> rotated component of each direction
+          const int qx = hydro_comp(s, 0), qy = hydro_comp(s, 1), qz = hydro_comp(s, 2);
+          const T acc = flux_delta<T, NDIM>(cdx, F.f[0][qx][e + 1], F.f[0][qx][e], cdy, F.f[1][qy][e + st[1]],
+                                            F.f[1][qy][e], cdz, NDIM == 3 ? F.f[2][qz][e + st[2]] : T(0),
+                                            NDIM == 3 ? F.f[2][qz][e] : T(0));
           Uout.f[s][e] = Uin.f[s][e] - acc;
         }
         if (NDIM == 2) {
           // cell-centred Bz: x-flux component t2 (index 6), y-flux component t1 (index 5)
-          T acc = cdx * (F.f[0][6][e + 1] - F.f[0][6][e]) + cdy * (F.f[1][5][e + st[1]] - F.f[1][5][e]);
+          const T acc = flux_delta<T, 2>(cdx, F.f[0][6][e + 1], F.f[0][6][e], cdy, F.f[1][5][e + st[1]],
+                                         F.f[1][5][e], T(0), T(0), T(0));
           Uout.f[7][e] = Uin.f[7][e] - acc;
         }
       }
@@ -368,28 +284,28 @@ __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ gri
         if (cy < uhy && k < uhz) {  // Bx face (cx, cy, k)
           T ez0 = emf_at<2, UPWIND>(F, e, st), ez1 = emf_at<2, UPWIND>(F, e + st[1], st);
           T ey0 = emf_at<1, UPWIND>(F, e, st), ey1 = emf_at<1, UPWIND>(F, e + st[2], st);
-          Uout.f[5][e] = Uin.f[5][e] - (cdy * (ez1 - ez0) - cdz * (ey1 - ey0));
+          Uout.f[5][e] = Uin.f[5][e] - curl_delta(cdy, ez1, ez0, cdz, ey1, ey0);
         }
         if (cx < uhx && k < uhz) {  // By face
           T ex0 = emf_at<0, UPWIND>(F, e, st), ex1 = emf_at<0, UPWIND>(F, e + st[2], st);
           T ez0 = emf_at<2, UPWIND>(F, e, st), ez1 = emf_at<2, UPWIND>(F, e + st[0], st);
-          Uout.f[6][e] = Uin.f[6][e] - (cdz * (ex1 - ex0) - cdx * (ez1 - ez0));
+          Uout.f[6][e] = Uin.f[6][e] - curl_delta(cdz, ex1, ex0, cdx, ez1, ez0);
         }
         if (cx < uhx && cy < uhy) {  // Bz face
           T ey0 = emf_at<1, UPWIND>(F, e, st), ey1 = emf_at<1, UPWIND>(F, e + st[0], st);
           T ex0 = emf_at<0, UPWIND>(F, e, st), ex1 = emf_at<0, UPWIND>(F, e + st[1], st);
-          Uout.f[7][e] = Uin.f[7][e] - (cdx * (ey1 - ey0) - cdy * (ex1 - ex0));
+          Uout.f[7][e] = Uin.f[7][e] - curl_delta(cdx, ey1, ey0, cdy, ex1, ex0);
         }
       } else {
         // 2D: only E_z; edges are cell corners.
         auto ez = [&](int64_t ee) { return emf_at<2, UPWIND>(F, ee, st); };
         if (cy < uhy) {  // Bx face
           T e0 = ez(e), e1 = ez(e + st[1]);
-          Uout.f[5][e] = Uin.f[5][e] - cdy * (e1 - e0);
+          Uout.f[5][e] = Uin.f[5][e] - face_delta2(cdy, e1, e0);
         }
         if (cx < uhx) {  // By face
           T e0 = ez(e), e1 = ez(e + st[0]);
-          Uout.f[6][e] = Uin.f[6][e] + cdx * (e1 - e0);
+          Uout.f[6][e] = Uin.f[6][e] + face_delta2(cdx, e1, e0);
         }
       }
     }

@@ -125,5 +125,14 @@ void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int ni
 template <class T>
 void launch_emf(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevFlux<T> F, hipStream_t s);
 template <class T> void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_cu);
+// Fused flux + update launch over fused work items (tiles overlapping by two
+// columns and rows; see fused.hip).  fmask (may be null): per element, bit d
+// set where the face flux normal to d must also be stored in F (the
+// coarse/fine registers read it).
+template <class T>
+void launch_fused(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
+                  uint32_t parity, DevFlux<T> F, const uint8_t* fmask, const double* dt0, Phys ph, ErrBlock* err,
+                  WorkQueue* q, int pblocks, bool xcd, hipStream_t s);
+template <class T> int fused_occupancy(int ndim);
 
 }  // namespace amr

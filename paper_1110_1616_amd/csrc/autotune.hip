@@ -43,12 +43,12 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
   }
   do_dt<T>(h, Ua, Ub, parity, dt0, s);
   const int zc[4] = {8, 12, 16, 32};
-  const int modes[6] = {0, 1, 2, 3, 4, 6};
+  const int modes[10] = {0, 1, 2, 3, 4, 6, 8, 10, 12, 14};
   int best = -1, n = 0, bpol = 1, bzc = 8, bmode = 0;
   double best_ms = 0.0;
   for (int pol = 0; pol < 2; ++pol)
     for (int zi = 0; zi < 4; ++zi)
-      for (int mi = 0; mi < 6; ++mi, ++n) {
+      for (int mi = 0; mi < 10; ++mi, ++n) {
         set_launch_config(h, pol, zc[zi], modes[mi]);
         const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
         if (out) out[n] = amr_tune_entry{pol, zc[zi], modes[mi], h->upd_zchunk, ms};

@@ -6,6 +6,49 @@
 
 namespace amr {
 
+// The update's arithmetic, shared by the update kernel, the fused
+// flux-update kernel and the registers so that all of them produce the same
+// bits: no multiply-add contraction here (it would otherwise depend on the
+// code each is inlined into).  Edge EMF from the four face values around the
+// edge: b_lo, b_hi the B_t1 flux component on the two b-faces, c_lo, c_hi
+// the B_t2 component on the two c-faces (low side first).
+template <class T> __device__ __forceinline__ T emf_mean(T b_lo, T b_hi, T c_lo, T c_hi) {
+#pragma clang fp contract(off)
+  const T s1 = b_lo + b_hi;
+  const T s2 = c_lo + c_hi;
+  return T(0.25) * (s2 - s1);
+}
+// Flux difference of a cell field over its faces: cdx (F_x,high - F_x,low) +
+// cdy (...) [+ cdz (...) in 3-D].
+template <class T, int NDIM>
+__device__ __forceinline__ T flux_delta(T cdx, T xh, T xl, T cdy, T yh, T yl, T cdz, T zh, T zl) {
+#pragma clang fp contract(off)
+  T acc = cdx * (xh - xl) + cdy * (yh - yl);
+  if (NDIM == 3) acc += cdz * (zh - zl);
+  return acc;
+}
+// Curl term of a face update: c1 (a1 - a0) - c2 (b1 - b0); in 2-D the
+// single term c (a1 - a0).
+template <class T> __device__ __forceinline__ T curl_delta(T c1, T a1, T a0, T c2, T b1, T b0) {
+#pragma clang fp contract(off)
+  return c1 * (a1 - a0) - c2 * (b1 - b0);
+}
+template <class T> __device__ __forceinline__ T face_delta2(T c, T a1, T a0) {
+#pragma clang fp contract(off)
+  return c * (a1 - a0);
+}
+// Updated value u - d (kept apart from the products above).
+template <class T> __device__ __forceinline__ T sub_nc(T u, T d) {
+#pragma clang fp contract(off)
+  return u - d;
+}
+// Rotated flux component of direction d that carries lab conserved slot s
+// (0..4): density and energy keep their slot; momentum a = s - 1 is the
+// normal (1), first (2) or second (3) tangential component.
+__host__ __device__ __forceinline__ int hydro_comp(int s, int d) {
+  return (s == 0 || s == 4) ? s : 1 + (s - 1 + 3 - d) % 3;
+}
+
 // EMF along axis A at the edge whose high-side cell (in the two other axes)
 // has element e: the mean of the four adjacent face values, E_A = -F_b(B_c)
 // on b-faces and +F_c(B_b) on c-faces (b = A+1, c = A+2; rotated flux
@@ -13,9 +56,7 @@ namespace amr {
 template <int A, class T>
 __device__ __forceinline__ T edge_emf(const DevFlux<T>& F, int64_t e, const int64_t (&st)[3]) {
   constexpr int B = (A + 1) % 3, C = (A + 2) % 3;
-  T s1 = F.f[B][5][e - st[C]] + F.f[B][5][e];
-  T s2 = F.f[C][6][e - st[B]] + F.f[C][6][e];
-  return T(0.25) * (s2 - s1);
+  return emf_mean(F.f[B][5][e - st[C]], F.f[B][5][e], F.f[C][6][e - st[B]], F.f[C][6][e]);
 }
 
 // Upwinded EMF (Gardiner & Stone 2005, J. Comput. Phys. 205, 509) at the

@@ -43,6 +43,21 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     e2 = h->take_event();
     HIPCHK(hipEventRecord(h->ev_pool[e0], s));
   }
+  if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+    if (h->fused && !h->upwind_emf) {
+      // one fused flux-update launch; the update's event pair measures zero
+      launch_fused<T>(h->ndim, h->d_desc, h->d_xitems + L.fused.off, L.fused.n, s0, s1, parity, F, h->d_fmask, dt0, ph,
+                      h->d_err, h->d_queue, h->persistent_flux ? h->fused_pblocks : 0, h->xcd_chunks, s);
+      HIPCHK(hipGetLastError());
+      if (timing) {
+        HIPCHK(hipEventRecord(h->ev_pool[e1], s));
+        HIPCHK(hipEventRecord(h->ev_pool[e2], s));
+        h->ev_pairs[0].push_back({e0, e1});
+        h->ev_pairs[1].push_back({e1, e2});
+      }
+      return;
+    }
+  }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
                  h->d_queue, h->persistent_flux ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
@@ -283,6 +298,8 @@ amr_status amr_create(const amr_params* p, const amr_grid* grids, int32_t ngrids
         kernel_occupancy<float>(h->ndim, &fb, &ub);
       h->flux_pblocks = prop.multiProcessorCount * fb;
       h->upd_pblocks = prop.multiProcessorCount * ub;
+      h->fused_pblocks = prop.multiProcessorCount *
+                         (h->esize == 8 ? fused_occupancy<double>(h->ndim) : fused_occupancy<float>(h->ndim));
       h->device = dev;
       scratch_init_device(dev);
     }
@@ -656,7 +673,8 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
   if (tile_policy) *tile_policy = h->tile_policy;
   if (zchunk) *zchunk = h->zchunk;
   if (launch_mode)
-    *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0) | (h->persistent_flux && !h->persistent ? 4 : 0);
+    *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0) | (h->persistent_flux && !h->persistent ? 4 : 0) |
+                 (h->fused ? 8 : 0);
   return AMR_OK;
 }
 

@@ -67,6 +67,7 @@ struct ListRef {
 
 struct LaunchList {
   ListRef flux, upd, emf;
+  ListRef fused;  // the same grid steps as fused flux-update items
 };
 
 }  // namespace amrrt
@@ -97,6 +98,14 @@ struct amr_hierarchy {
   std::vector<UpdItem> h_eitems;
   std::vector<FluxItem> h_fitems;
   std::vector<UpdItem> h_uitems;
+  FluxItem* d_xitems = nullptr;  // fused flux-update items
+  std::vector<FluxItem> h_xitems;
+  // per element: bit d where a coarse/fine register reads the face flux
+  // normal to d (the fused kernel stores only those)
+  std::vector<uint8_t> h_fmask;
+  uint8_t* d_fmask = nullptr;
+  bool fused = false;  // launch mode bit 3: one fused flux-update kernel per launch
+  int fused_pblocks = 0;
   int4* d_cfl = nullptr;
   int n_cfl = 0;
   ErrBlock* d_err = nullptr;  // error block + CFL accumulator (handle-owned)
@@ -181,6 +190,8 @@ struct amr_hierarchy {
     (void)hipFree(d_fitems);
     (void)hipFree(d_uitems);
     (void)hipFree(d_eitems);
+    (void)hipFree(d_xitems);
+    (void)hipFree(d_fmask);
     (void)hipFree(d_cfl);
     (void)hipFree(d_err);
     (void)hipFree(d_queue);

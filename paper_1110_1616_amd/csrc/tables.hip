@@ -117,6 +117,27 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
         it.z1 = h->ndim == 3 ? std::min(z0 + uzc, uzhi) : 1;
         ul.push_back(it);
       }
+  // fused flux-update tiles: each owns (tw - 2) x (th - 2) cells of the
+  // update region (tiles overlap by two) and the z-planes [z0, z1) of the
+  // update's planes [ul, uh_z] (the top plane holds z-faces only)
+  if (!h->upwind_emf) {
+    const int xtw = pick_tile(uh[0] - ul0, uh[1] - ul0, 2, h->tile_policy), xth = 256 / xtw;
+    check_tile(xtw);
+    const int xzhi = h->ndim == 3 ? uh[2] + 1 : 1;
+    for (int z0 = uzlo; z0 < xzhi; z0 += (h->ndim == 3 ? zc : 1))
+      for (int y0 = ul0; y0 < uh[1]; y0 += xth - 2)
+        for (int x0 = ul0; x0 < uh[0]; x0 += xtw - 2) {
+          FluxItem it{};
+          it.tw = xtw;
+          it.grid = gi;
+          it.gv = gv;
+          it.x0 = x0;
+          it.y0 = y0;
+          it.z0 = z0;
+          it.z1 = h->ndim == 3 ? std::min(z0 + zc, xzhi) : 1;
+          h->h_xitems.push_back(it);
+        }
+  }
   if (!h->upwind_emf) return;
   // upwinded edge EMFs: the update's planes, one more column and row (the
   // update reads the edges at e and e + 1 along both transverse axes)
@@ -142,8 +163,10 @@ LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& g
   L.flux.off = (int)h->h_fitems.size();
   L.upd.off = (int)h->h_uitems.size();
   L.emf.off = (int)h->h_eitems.size();
+  L.fused.off = (int)h->h_xitems.size();
   for (auto& gb : grid_bands) add_grid_items(h, gb.first, gb.second, h->h_fitems, h->h_uitems);
   L.emf.n = (int)h->h_eitems.size() - L.emf.off;
+  L.fused.n = (int)h->h_xitems.size() - L.fused.off;
   L.flux.n = (int)h->h_fitems.size() - L.flux.off;
   L.upd.n = (int)h->h_uitems.size() - L.upd.off;
   // longest flux items first inside each eighth of the list (the XCD chunks
@@ -154,6 +177,12 @@ LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& g
   for (int c = 0; c < 8 && c * C < L.flux.n; ++c) {
     auto b = h->h_fitems.begin() + L.flux.off + c * C;
     auto e = h->h_fitems.begin() + L.flux.off + std::min(L.flux.n, (c + 1) * C);
+    std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
+  }
+  const int CX = (L.fused.n + 7) / 8;
+  for (int c = 0; c < 8 && c * CX < L.fused.n; ++c) {
+    auto b = h->h_xitems.begin() + L.fused.off + c * CX;
+    auto e = h->h_xitems.begin() + L.fused.off + std::min(L.fused.n, (c + 1) * CX);
     std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
   }
   return L;
@@ -294,6 +323,7 @@ void build_lists(amr_hierarchy* h) {
   h->d_fitems = dev_upload(h->h_fitems);
   h->d_uitems = dev_upload(h->h_uitems);
   h->d_eitems = dev_upload(h->h_eitems);
+  h->d_xitems = dev_upload(h->h_xitems);
   // CFL items: (grid, interior plane, first row, rows), about 1k cells each
   std::vector<int4> cf;
   for (int gi = 0; gi < (int)h->grids.size(); ++gi) {
@@ -876,6 +906,29 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   }
   T.nfreg = nfreg;
   T.nereg = (int)edge_id.size();
+  // face fluxes the registers read (the fused kernel stores only these)
+  {
+    if (h->h_fmask.empty()) h->h_fmask.assign(h->total_elems, 0);
+    auto mark = [&](int64_t e, int d) {
+      if (e < 0 || e >= h->total_elems) throw Error(AMR_EINVAL, "internal: register face outside the pools");
+      h->h_fmask[e] |= (uint8_t)(1u << d);
+    };
+    for (const auto* v : {&frc, &frf})
+      for (const FaceRegEntry& r : *v)
+        for (int i = 0; i < r.n; ++i) mark(r.e[i], r.d);
+    for (const auto* v : {&erc, &erf})
+      for (const EdgeRegEntry& r : *v) {
+        const GridDesc& G = h->desc[r.grid];
+        const int64_t st[3] = {1, G.P[0], h->ndim == 3 ? (int64_t)G.P[0] * G.P[1] : 0};
+        const int B = (r.a + 1) % 3, C = (r.a + 2) % 3;
+        for (int i = 0; i < r.n; ++i) {
+          mark(r.e[i] - st[C], B);
+          mark(r.e[i], B);
+          mark(r.e[i] - st[B], C);
+          mark(r.e[i], C);
+        }
+      }
+  }
   T.d_freg_c = dev_upload(frc);
   T.n_freg_c = (int)frc.size();
   T.d_freg_f = dev_upload(frf);
@@ -947,6 +1000,11 @@ amr_hierarchy* build_hierarchy(const amr_params* p, const amr_grid* grids, int32
       reg_bytes += (h->sync[l].reg_bytes + 255) / 256 * 256;
     }
     h->workspace_bytes = h->reg_offset + reg_bytes;
+    h->d_fmask = dev_upload(h->h_fmask);
+    if (!g_host_only) {  // host-only builds keep it for amr_selfcheck_addressing
+      h->h_fmask.clear();
+      h->h_fmask.shrink_to_fit();
+    }
     h->adj.resize(h->nlev);
     return h;
   } catch (...) {
@@ -965,6 +1023,9 @@ void rebuild_lists(amr_hierarchy* h) {
   HIPCHK(hipFree(h->d_eitems));
   h->d_eitems = nullptr;
   h->h_eitems.clear();
+  HIPCHK(hipFree(h->d_xitems));
+  h->d_xitems = nullptr;
+  h->h_xitems.clear();
   HIPCHK(hipFree(h->d_cfl));
   h->d_fitems = nullptr;
   h->d_uitems = nullptr;
@@ -990,10 +1051,11 @@ void set_update_zchunk(amr_hierarchy* h, int zchunk) {
 void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
   if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
-  if (mode < 0 || mode > 7) throw Error(AMR_EINVAL, "launch mode must be in [0, 7]");
+  if (mode < 0 || mode > 15) throw Error(AMR_EINVAL, "launch mode must be in [0, 15]");
   h->persistent = (mode & 1) != 0;
   h->persistent_flux = (mode & 5) != 0;
   h->xcd_chunks = (mode & 2) != 0;
+  h->fused = (mode & 8) != 0;
   if (policy != h->tile_policy || zchunk != h->zchunk) {
     h->tile_policy = policy;
     h->zchunk = zchunk;
