@@ -6,7 +6,8 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-
 Prints ONE JSON line.  `value` is useful cell-updates per second (one
 interior cell advanced by one (sub)step) of the whole step with inputs
 resident in HBM; the roofline object reports the dominant kernel (the flux
-kernel: primitive recovery, minmod slopes, Hancock predictor and HLLD) against
+kernel: primitive recovery, minmod slopes, Hancock predictor and HLLD, or the
+fused flux-update kernel when the launch configuration selects it) against
 the FP64 vector peak, its duration measured live with HIP events on the
 launch stream.  cpu_baseline times the FP64 oracle on a bounded sample of the
 same workload on the host cores.
@@ -32,6 +33,12 @@ PEAK_HBM_GBS = 8000.0
 # and one HLLD evaluation per face.  Checked against the oracle by a test.
 FLOPS_PRED = {3: 912, 2: 612}
 FLOPS_HLLD = 367
+# The update's share, counted the same way: per updated cell (the hydro
+# components, and B_z in 2-D), per updated face-centred B component, and per
+# edge EMF (arithmetic mean of the four face EMFs).
+FLOPS_UPD_CELL = {3: 55, 2: 48}
+FLOPS_UPD_FACE = {3: 8, 2: 5}
+FLOPS_EMF_EDGE = 4
 GAMMA = 5.0 / 3.0
 
 
@@ -46,28 +53,38 @@ def cpu_model():
     return None
 
 
-def kernel_source_digest():
-    """sha256 over the sources that define the flux kernel's memory traffic
-    (the kernels and the host code that builds their work lists)."""
+KERNEL_SOURCES = {
+    "k_flux": ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp", "tables.hip"),
+    "k_fused": ("fused.hip", "launch_common.hpp", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp",
+                "emf.hpp", "tables.hip"),
+}
+
+
+def kernel_source_digest(kernel="k_flux"):
+    """sha256 over the sources that define a kernel's memory traffic (the
+    kernel and the host code that builds its work lists)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("advance.hip", "advance_common.hpp", "mhd_device.hpp", "amr_internal.hpp", "emf.hpp", "tables.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1110_1616_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload, dtype):
-    """HBM bytes per flux-kernel launch from the committed rocprofv3 counter
+def measured_traffic(workload, dtype, kernel="k_flux", launch_config=None):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what
-    the counter reads for a copy of known size), or None if there is none or
-    the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"k_flux_{workload}_traffic.json")
+    the counter reads for a copy of known size), or None if there is none,
+    it was taken in another launch configuration, or the kernel sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256") != kernel_source_digest() or rec.get("dtype") != dtype:
+    if rec.get("source_sha256") != kernel_source_digest(kernel) or rec.get("dtype") != dtype:
+        return None
+    if launch_config is not None and rec.get("launch_config") != launch_config:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -87,6 +104,28 @@ def flux_kernel_flops(ndim, n, gv):
                 f *= m[a]
         faces += f
     return FLOPS_PRED[ndim] * cells + FLOPS_HLLD * faces
+
+
+def update_flops(ndim, n, gv):
+    """Algorithmic flops of the update over a grid with interior n advanced
+    from valid band gv: the updated box reaches gv - 2 cells into the band."""
+    u = [x + 2 * gv - 4 for x in n[:ndim]]
+    cells = 1
+    for x in u:
+        cells *= x
+    faces = edges = 0
+    for d in range(ndim):
+        f = u[d] + 1
+        e = u[d]
+        for a in range(ndim):
+            if a != d:
+                f *= u[a]
+                e *= u[a] + 1
+        faces += f
+        edges += e
+    if ndim == 2:
+        edges = (u[0] + 1) * (u[1] + 1)  # E_z only
+    return FLOPS_UPD_CELL[ndim] * cells + FLOPS_UPD_FACE[ndim] * faces + FLOPS_EMF_EDGE * edges
 
 
 def single_grid_workload(args):
@@ -120,6 +159,7 @@ def single_grid_workload(args):
         state["s"] = s + 1
 
     flops_per_step_pair = flux_kernel_flops(3, n, 4) + flux_kernel_flops(3, n, 2)
+    upd_per_step_pair = update_flops(3, n, 4) + update_flops(3, n, 2)
     info = {
         "workload": f"single 3D grid {N}^3 + 4-cell band, ideal MHD {dtype}, smooth Fourier-mode rho/v/A "
                     f"(|B| rms 0.3) with a 4:1 planar density jump, periodic, CFL 0.4",
@@ -139,7 +179,8 @@ def single_grid_workload(args):
     def tune():
         return H.autotune(state["U"], state["V"], 0, reps=3)
 
-    return H, step, (lambda k: flops_per_step_pair * k / 2.0), info, cpu_sample, tune
+    return (H, step, (lambda k: flops_per_step_pair * k / 2.0), (lambda k: upd_per_step_pair * k / 2.0), info,
+            cpu_sample, tune)
 
 
 def amr_workload(args, deep=False):
@@ -176,13 +217,15 @@ def amr_workload(args, deep=False):
     for (l, lo, hi) in grids:
         cells[l] += int(np.prod([hi[a] - lo[a] for a in range(3)]))
     updates = sum(c * 2 ** l for l, c in enumerate(cells))
-    # algorithmic flops of the flux kernel per coarse step
-    fl = 0
+    # algorithmic flops of the flux kernel (fl) and of the update (ufl) per
+    # coarse step
+    fl = ufl = 0
     for (l, lo, hi) in grids:
         n = [hi[a] - lo[a] for a in range(3)]
         for k in range(2 ** l):
             gv = 2 if l == 0 else 4 - 2 * (k % 2)
             fl += flux_kernel_flops(3, n, gv)
+            ufl += update_flops(3, n, gv)
     st = {"par": 0}
     stream = torch.cuda.Stream()
 
@@ -293,14 +336,15 @@ def amr_workload(args, deep=False):
                 "cell_updates_per_s_after": sum(c * 2 ** l for l, c in enumerate(c2)) / (e0.elapsed_time(e1) / 3e3)}
 
     return {"H": H, "stream": stream, "step": graph_step, "prepare": capture, "eager": eager(0),
-            "per_grid": eager(1), "prepare_per_grid": capture_per_grid, "flux_flops": lambda k: fl * k, "info": info, "cpu_sample": cpu_sample,
+            "per_grid": eager(1), "prepare_per_grid": capture_per_grid, "flux_flops": lambda k: fl * k,
+            "update_flops": lambda k: ufl * k, "info": info, "cpu_sample": cpu_sample,
             "tune": tune, "regrid": None if deep else regrid_measure, "schedules": True}
 
 
 def single_workload(args):
-    H, step, flops, info, cpu, tune = single_grid_workload(args)
+    H, step, flops, uflops, info, cpu, tune = single_grid_workload(args)
     return {"H": H, "stream": None, "step": step, "prepare": None, "eager": step, "per_grid": None,
-            "flux_flops": flops, "info": info, "cpu_sample": cpu, "tune": tune}
+            "flux_flops": flops, "update_flops": uflops, "info": info, "cpu_sample": cpu, "tune": tune}
 
 
 EMF = {"mean": 0, "upwind": 1}
@@ -390,7 +434,7 @@ def main():
                     help="largest box extent of the measured regrid, in level-1 cells")
     ap.add_argument("--launch-config", default=None,
                     help="tile_policy,zchunk,launch_mode[,update_zchunk]: set this launch configuration instead "
-                         "of autotuning (launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD, bit 2 persistent flux kernel only)")
+                         "of autotuning (launch_mode bit 0 persistent queue, bit 1 one item chunk per XCD, bit 2 persistent flux kernel only, bit 3 fused flux-update kernel, bits 4-5 log2 of the work items per block claim)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a plain copy kernel of known size that "
                          "calibrates HBM byte counters)")
@@ -520,9 +564,15 @@ def main():
     seconds = gpu_ms / 1e3
     updates = float(info["cells"]) * args.steps
     value = updates / seconds
-    fl = W["flux_flops"](args.steps)
+    # the dominant kernel: the flux kernel, or the fused flux-update kernel
+    # (launch mode bit 3), whose event pair then covers the whole advance
+    pol, zc, mode = A.amr_get_launch_config(H.h)
+    fused = bool(mode & 8) and args.emf == "mean"
+    kname = "k_fused" if fused else "k_flux"
+    fl = W["flux_flops"](args.steps) + (W["update_flops"](args.steps) if fused else 0.0)
     peak = PEAK_FP64_VECTOR_TFLOPS if info["dtype"] == "f64" else PEAK_FP32_VECTOR_TFLOPS
     achieved = fl / (flux_ms / 1e3) / 1e12
+    cfg = f"{pol},{zc},{mode}"
     esize = 8 if info["dtype"] == "f64" else 4
     out = {
         "metric": "MHD cell-updates/s (useful interior cell-updates per second of the batched advance)",
@@ -540,11 +590,13 @@ def main():
         "config": {"workload": info["workload"] + ("; upwinded (Gardiner-Stone) CT EMF" if args.emf == "upwind" else ""),
                    "grids": info["grids"],
                    "useful_cell_updates_per_step": info["cells"], "parallelism": "single GPU"},
-        "roofline": {"kernel": "k_flux", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(args.workload, info["dtype"]),
-                     "avg_launch_ms": flux_ms / max(nl, 1), "launches": nl},
-        "kernels_ms_per_step": {"k_flux": flux_ms / args.steps, "k_update": upd_ms / args.steps},
+                     "traffic": measured_traffic(args.workload, info["dtype"], kname, cfg),
+                     "avg_launch_ms": flux_ms / max(nl, 1), "launches": nl, "launch_config": cfg,
+                     "flops_per_launch": fl / max(nl, 1)},
+        "kernels_ms_per_step": ({"k_fused": flux_ms / args.steps} if fused else
+                                {"k_flux": flux_ms / args.steps, "k_update": upd_ms / args.steps}),
         "eager_value": updates / (eager_ms / 1e3),
         "hbm_algorithmic_GBps": updates * 16 * esize / seconds / 1e9,
         "wall_s": wall,

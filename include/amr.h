@@ -328,10 +328,10 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * per tile) that launches the fewest tiles over the grid.  zchunk: planes per
  * work item along z (3D).  launch_mode bit 0: persistent launches (a fixed
  * grid of resident blocks popping the launch's item list from a device
- * queue, one atomic per item, in list order: finest level first, then inside
- * each eighth of the flux list its longest items (most z-planes) first; the
- * queue resets itself at the end of each launch), else one block per work
- * item;
+ * queue, one atomic per claim of items, in list order: finest level first,
+ * then inside each eighth of the flux list its longest items (most
+ * z-planes) first; the queue resets itself at the end of each launch), else
+ * one block per claim;
  * bit 1: the item list is cut into 8 contiguous chunks, one per XCD
  * (workgroups reach the XCDs round-robin, so chunk c runs on XCD c and
  * neighbouring tiles share its L2; persistent blocks drain their own chunk
@@ -340,8 +340,11 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * bit 3: one fused flux-update kernel per launch instead of the two (tiles
  * overlapping by two cells, face fluxes kept in LDS; only those the
  * coarse/fine registers read are stored; persistent with bit 0 or 2; the
- * upwinded EMF always takes the two-kernel path).  launch_mode in [0, 15],
- * else AMR_EINVAL.  The two-kernel configurations give bitwise identical
+ * upwinded EMF always takes the two-kernel path); bits 4-5: c, each block
+ * takes 2^c consecutive work items at a time (grids per workgroup for grids
+ * of one tile and one z-chunk; else a run of neighbouring tiles), for every
+ * kernel of the launch.  launch_mode in [0, 63], else AMR_EINVAL; the claim
+ * size never changes results.  The two-kernel configurations give bitwise identical
  * results, and so do the fused ones of one tile policy; in FP64 the fused
  * kernel differs from the two-kernel path, and between tile policies, by an
  * ulp here and there (the same expressions, compiled with different
@@ -359,7 +362,7 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
 amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk);
 amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk);
 
-#define AMR_TUNE_CANDIDATES 84
+#define AMR_TUNE_CANDIDATES 87
 
 typedef struct {
   int32_t tile_policy, zchunk, launch_mode, update_zchunk;
@@ -371,9 +374,11 @@ typedef struct {
  * times the 80 configurations tile_policy x zchunk in {8, 12, 16, 32} x
  * launch_mode in {0, 1, 2, 3, 4, 6, 8, 10, 12, 14} (entries 0..79, under the
  * current update z-chunk), keeps the fastest, and under it times the update
- * z-chunks {1, 2, 4, 8} (entries 80..83), each over `reps` passes of every
- * launch cycle's batched advance, reading each level's current buffer
- * (parity) and writing the other one, and keeps the fastest of all 84.  The state the
+ * z-chunks {1, 2, 4, 8} (entries 80..83) and then, under the kept update
+ * z-chunk, claims of 2, 4 and 8 items per block (launch mode bits 4-5,
+ * entries 84..86), each over `reps` passes of every launch cycle's batched
+ * advance, reading each level's current buffer (parity) and writing the
+ * other one, and keeps the fastest of all 87.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */

@@ -320,7 +320,7 @@ def amr_get_update_zchunk(h):
     return a.value
 
 
-TUNE_CANDIDATES = 84
+TUNE_CANDIDATES = 87
 
 
 def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):

@@ -28,9 +28,9 @@ template <class T, int NDIM, bool PERSIST, bool UPWIND>
 __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                               DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, ErrBlock* err,
-                                              WorkQueue* q, bool xcd) {
+                                              WorkQueue* q, bool xcd, int claim) {
   __shared__ T sW[8][kMaxPlane];
-  __shared__ int s_it, s_c;
+  __shared__ int s_claim[2], s_c;
   if (threadIdx.x == 0) s_c = 0;
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
@@ -39,9 +39,9 @@ __global__ __launch_bounds__(256) void k_flux(const GridDesc* __restrict__ grids
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
 
-  int cursor = blockIdx.x;
+  ItemRange rng = first_claim<PERSIST>(nitems, claim, xcd);
   for (;;) {
-    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it, &s_c, xcd);
+    const int it = next_item<PERSIST>(rng, nitems, claim, q, s_claim, &s_c, xcd);
     if (it < 0) break;
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -226,13 +226,13 @@ template <class T, int NDIM, bool PERSIST, bool UPWIND>
 __global__ __launch_bounds__(256) void k_update(const GridDesc* __restrict__ grids, const UpdItem* __restrict__ items,
                                                 int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                                 DevFlux<T> F, const double* __restrict__ dt0p, Phys ph, WorkQueue* q,
-                                                bool xcd) {
-  __shared__ int s_it, s_c;
+                                                bool xcd, int claim) {
+  __shared__ int s_claim[2], s_c;
   if (threadIdx.x == 0) s_c = 0;
   const int tid = threadIdx.x;
-  int cursor = blockIdx.x;
+  ItemRange rng = first_claim<PERSIST>(nitems, claim, xcd);
   for (;;) {
-    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it, &s_c, xcd);
+    const int it = next_item<PERSIST>(rng, nitems, claim, q, s_claim, &s_c, xcd);
     if (it < 0) break;
     const UpdItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -344,13 +344,13 @@ __global__ __launch_bounds__(256) void k_emf(const GridDesc* __restrict__ grids,
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 bool xcd, bool upwind_emf, hipStream_t s) {
+                 bool xcd, int claim, bool upwind_emf, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
-  const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
+  const dim3 grid(per ? std::min(pblocks, nitems) : claim_blocks(nitems, claim, xcd)), block(256);
 #define AMR_FLUX_LAUNCH(ND, P, U)                                                                                  \
   hipLaunchKernelGGL((k_flux<T, ND, P, U>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, err, \
-                     q, xcd)
+                     q, xcd, claim)
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
     if (upwind_emf) {
       if (ndim == 3) {
@@ -376,13 +376,13 @@ void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nit
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   bool xcd, bool upwind_emf, hipStream_t s) {
+                   bool xcd, int claim, bool upwind_emf, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
-  const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
+  const dim3 grid(per ? std::min(pblocks, nitems) : claim_blocks(nitems, claim, xcd)), block(256);
 #define AMR_UPD_LAUNCH(ND, P, U)                                                                                   \
   hipLaunchKernelGGL((k_update<T, ND, P, U>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, dt0, ph, q, \
-                     xcd)
+                     xcd, claim)
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
     if (upwind_emf) {
       if (ndim == 3) {
@@ -433,9 +433,10 @@ void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int* update_blocks_per_
 
 #define AMR_ADV_INST(T)                                                                                             \
   template void launch_flux<T>(int, const GridDesc*, const FluxItem*, int, DevState<T>, DevState<T>, uint32_t,     \
-                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, bool, hipStream_t); \
+                               DevFlux<T>, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, int, bool,          \
+                               hipStream_t);                                                                       \
   template void launch_update<T>(int, const GridDesc*, const UpdItem*, int, DevState<T>, DevState<T>, uint32_t,   \
-                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, bool, bool, hipStream_t);
+                                 DevFlux<T>, const double*, Phys, WorkQueue*, int, bool, int, bool, hipStream_t);
 AMR_ADV_INST(float)
 AMR_ADV_INST(double)
 // frozen-branch instances (finite-difference verification of the adjoint)

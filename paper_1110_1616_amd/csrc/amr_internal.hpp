@@ -110,16 +110,16 @@ struct WorkQueue {
 // Level l of a grid reads its state from S1 if bit l of `parity` is set,
 // else from S0; the update writes the other one.
 // pblocks > 0 (with a queue): a persistent launch of pblocks blocks that pop
-// the items; else one block per item.  xcd: items in 8 contiguous chunks, one
-// per XCD.
+// the items; else one block per claim.  xcd: items in 8 contiguous chunks,
+// one per XCD.  claim: items a block takes at a time (1, 2, 4 or 8).
 template <class T>
 void launch_flux(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                  uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, ErrBlock* err, WorkQueue* q, int pblocks,
-                 bool xcd, bool upwind_emf, hipStream_t s);
+                 bool xcd, int claim, bool upwind_emf, hipStream_t s);
 template <class T>
 void launch_update(int ndim, const GridDesc* grids, const UpdItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                    uint32_t parity, DevFlux<T> F, const double* dt0, Phys ph, WorkQueue* q, int pblocks,
-                   bool xcd, bool upwind_emf, hipStream_t s);
+                   bool xcd, int claim, bool upwind_emf, hipStream_t s);
 // Upwinded edge EMFs of every edge the update reads (items: the update tiles
 // of the same grids, one column and row wider).
 template <class T>
@@ -132,7 +132,7 @@ template <class T> void kernel_occupancy(int ndim, int* flux_blocks_per_cu, int*
 template <class T>
 void launch_fused(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                   uint32_t parity, DevFlux<T> F, const uint8_t* fmask, const double* dt0, Phys ph, ErrBlock* err,
-                  WorkQueue* q, int pblocks, bool xcd, hipStream_t s);
+                  WorkQueue* q, int pblocks, bool xcd, int claim, hipStream_t s);
 template <class T> int fused_occupancy(int ndim);
 
 }  // namespace amr

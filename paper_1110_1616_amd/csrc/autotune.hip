@@ -75,6 +75,20 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
     }
   }
   set_update_zchunk(h, ubest);
+  // then the work items a block takes at a time (launch mode bits 4-5)
+  int cbest = bmode;
+  for (int ci = 1; ci <= 3; ++ci, ++n) {
+    const int mode = bmode | (ci << 4);
+    set_launch_config(h, bpol, bzc, mode);
+    const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);
+    if (out) out[n] = amr_tune_entry{bpol, bzc, mode, ubest, ms};
+    if (ms < best_ms) {
+      best = n;
+      best_ms = ms;
+      cbest = mode;
+    }
+  }
+  set_launch_config(h, bpol, bzc, cbest);
   return best;
 }
 

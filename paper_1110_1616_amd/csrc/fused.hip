@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
                                                int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
                                                DevFlux<T> F, const uint8_t* __restrict__ fmask,
                                                const double* __restrict__ dt0p, Phys ph, ErrBlock* err, WorkQueue* q,
-                                               bool xcd) {
+                                               bool xcd, int claim) {
   __shared__ T sW[8][kMaxPlane];
   __shared__ T sX[7][256];
   __shared__ T sY[7][256];
@@ -57,16 +57,16 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
   __shared__ T sB[4][256];      // EMF inputs of this plane: F_x c5, F_y c6, F_z c5, F_z c6 (2-D: F_x c6, F_y c5)
   __shared__ T sEz[2][256];     // E_z at each lane's (x, y) low corner, by plane parity
   __shared__ T sExy[2][256];    // E_x, E_y at each lane's low z-edges of the current level
-  __shared__ int s_it, s_c;
+  __shared__ int s_claim[2], s_c;
   if (threadIdx.x == 0) s_c = 0;
 
   const int tid = threadIdx.x;
   const T gam = T(ph.gamma);
   const T gm1 = gam - T(1);
 
-  int cursor = blockIdx.x;
+  ItemRange rng = first_claim<PERSIST>(nitems, claim, xcd);
   for (;;) {
-    const int it = next_item<PERSIST>(cursor, nitems, q, &s_it, &s_c, xcd);
+    const int it = next_item<PERSIST>(rng, nitems, claim, q, s_claim, &s_c, xcd);
     if (it < 0) break;
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
@@ -148,8 +148,13 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
     }
     __syncthreads();
 
+    uint8_t mknext = (fmask && act) ? fmask[ix(cx, cy, kstart)] : uint8_t(0);
     for (int k = kstart; k <= kend; ++k) {
       const int pb = k & 1;
+      // this plane's face mask was loaded an iteration ago; the next one's
+      // load is in flight through this iteration
+      const uint8_t mk = mknext;
+      if (fmask && act && k + 1 <= kend) mknext = fmask[ix(cx, cy, k + 1)];
       T rnext[5], rfb[3][2], rring[5], rrfb[3][2];
       const bool pf = NDIM == 3 && ook && k + 2 <= kend + 1;
       if (NDIM == 3) {
@@ -204,7 +209,6 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
       }
       const bool zf = NDIM == 3 && act && k >= z0;
       const auto eb = bx(cx, cy, k);
-      const uint8_t mk = (fmask && act) ? fmask[ix(cx, cy, k)] : uint8_t(0);
       T fx[7], fy[7], fz[7];
 #pragma unroll
       for (int c = 0; c < 7; ++c) { fx[c] = T(0); fy[c] = T(0); fz[c] = T(0); }
@@ -263,33 +267,45 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
       }
       __syncthreads();
       if (NDIM == 3) {
+        // the old values of everything this plane updates are loaded before
+        // any store, so their latencies overlap
+        const int kk = k - 1;
+        const bool zup = ucell && k >= z0 && k < z1;
+        const bool cup = kk >= z0 && kk < z1 && kk < uhz;
+        const auto ec = bx(cx, cy, kk);
+        T uo[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) uo[s] = T(0);
+        if (zup) uo[7] = ldb(U.f[7], eb);
+        if (cup && ucell)
+#pragma unroll
+          for (int s = 0; s < 5; ++s) uo[s] = ldb(U.f[s], ec);
+        if (cup && ubx) uo[5] = ldb(U.f[5], ec);
+        if (cup && uby) uo[6] = ldb(U.f[6], ec);
         // z-faces at k - 1/2 (element of plane k)
-        if (ucell && k >= z0 && k < z1) {
+        if (zup) {
           const T ey1 = sExy[1][tid + 1], ex1 = sExy[0][tid + tw];
-          const T v7 = ldb(U.f[7], eb);
-          stb(V.f[7], eb, v7 - curl_delta(cdx, ey1, ey, cdy, ex1, ex));
+          stb(V.f[7], eb, uo[7] - curl_delta(cdx, ey1, ey, cdy, ex1, ex));
         }
         // cells and x-, y-faces of plane k - 1
-        const int kk = k - 1;
-        if (kk >= z0 && kk < z1 && kk < uhz) {
+        if (cup) {
           const int qb = kk & 1;
-          const auto ec = bx(cx, cy, kk);
           if (ucell) {
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
               const int qx = hydro_comp(s, 0), qy = hydro_comp(s, 1), qz = hydro_comp(s, 2);
               const T acc = flux_delta<T, 3>(cdx, sH[qb][qx][tid + 1], sH[qb][qx][tid], cdy, sH[qb][5 + qy][tid + tw],
                                              sH[qb][5 + qy][tid], cdz, fz[qz], fzp[qz]);
-              stb(V.f[s], ec, ldb(U.f[s], ec) - acc);
+              stb(V.f[s], ec, uo[s] - acc);
             }
           }
           if (ubx) {
             const T ez0 = sEz[qb][tid], ez1 = sEz[qb][tid + tw];
-            stb(V.f[5], ec, ldb(U.f[5], ec) - curl_delta(cdy, ez1, ez0, cdz, ey, eyp_));
+            stb(V.f[5], ec, uo[5] - curl_delta(cdy, ez1, ez0, cdz, ey, eyp_));
           }
           if (uby) {
             const T ez0 = sEz[qb][tid], ez1 = sEz[qb][tid + 1];
-            stb(V.f[6], ec, ldb(U.f[6], ec) - curl_delta(cdz, ex, exp_, cdx, ez1, ez0));
+            stb(V.f[6], ec, uo[6] - curl_delta(cdz, ex, exp_, cdx, ez1, ez0));
           }
         }
 #pragma unroll
@@ -332,12 +348,13 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
 template <class T>
 void launch_fused(int ndim, const GridDesc* grids, const FluxItem* items, int nitems, DevState<T> S0, DevState<T> S1,
                   uint32_t parity, DevFlux<T> F, const uint8_t* fmask, const double* dt0, Phys ph, ErrBlock* err,
-                  WorkQueue* q, int pblocks, bool xcd, hipStream_t s) {
+                  WorkQueue* q, int pblocks, bool xcd, int claim, hipStream_t s) {
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
-  const dim3 grid(per ? std::min(pblocks, nitems) : (xcd ? 8 * ((nitems + 7) / 8) : nitems)), block(256);
+  const dim3 grid(per ? std::min(pblocks, nitems) : claim_blocks(nitems, claim, xcd)), block(256);
 #define AMR_FUSED_LAUNCH(ND, P) \
-  hipLaunchKernelGGL((k_fused<T, ND, P>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, fmask, dt0, ph, err, q, xcd)
+  hipLaunchKernelGGL((k_fused<T, ND, P>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, fmask, dt0, ph, err, q, xcd, \
+                     claim)
   if (ndim == 3) {
     if (per) AMR_FUSED_LAUNCH(3, true);
     else AMR_FUSED_LAUNCH(3, false);
@@ -360,7 +377,7 @@ template <class T> int fused_occupancy(int ndim) {
 #define AMR_FUSED_INST(T)                                                                                           \
   template void launch_fused<T>(int, const GridDesc*, const FluxItem*, int, DevState<T>, DevState<T>, uint32_t,    \
                                 DevFlux<T>, const uint8_t*, const double*, Phys, ErrBlock*, WorkQueue*, int, bool, \
-                                hipStream_t);                                                                      \
+                                int, hipStream_t);                                                                      \
   template int fused_occupancy<T>(int);
 AMR_FUSED_INST(float)
 AMR_FUSED_INST(double)

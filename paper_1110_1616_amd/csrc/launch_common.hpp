@@ -22,53 +22,91 @@ __device__ __forceinline__ void ring_entry(int r, int tw, int th, int& ex, int& 
   else { ex = tw + 1; ey = r - 2 * tw - th + 1; }
 }
 
-// Next work item of this block.  Grid-stride launches take blockIdx.x,
-// blockIdx.x + gridDim.x, ...; persistent launches (a fixed number of blocks)
-// pop the shared queue, one atomic per item, in list order (finest level
-// first), so blocks that draw cheap items come back for more.  With `xcd`
-// the list is cut into 8 contiguous chunks, one per XCD (workgroups are
-// dispatched to the 8 XCDs round-robin, so block b runs on XCD b mod 8):
-// neighbouring tiles, which share halo data, then run under one L2.  A
-// one-block-per-item launch maps block b to item (b mod 8) C + b / 8; a
-// persistent block pops its own chunk first, then the others.  Returns -1
-// when the list is exhausted.
+// Work items are handed to blocks in claims of `claim` consecutive list
+// entries (claim in {1, 2, 4, 8}): a block runs its claim's items back to
+// back and only then takes another.  Grids of one tile per plane and one
+// z-chunk are one item each, so for them the claim is the number of grids a
+// workgroup takes at a time; for larger grids it is a run of neighbouring
+// tiles of one grid.  A block's current claim is [next, end).
+struct ItemRange {
+  int next, end;
+};
+
+// Claim of a one-block-per-range launch (non-persistent): block b takes
+// entries [b claim, (b + 1) claim); with `xcd` the list is cut into 8
+// contiguous chunks of C entries, one per XCD (workgroups are dispatched to
+// the 8 XCDs round-robin, so block b runs on XCD b mod 8), and block b takes
+// the (b / 8)-th claim of chunk b mod 8, so neighbouring tiles, which share
+// halo data, run under one L2.  Persistent launches start with an empty
+// claim.
 template <bool PERSIST>
-__device__ __forceinline__ int next_item(int& cursor, int nitems, WorkQueue* q, int* s_it, int* s_c, bool xcd) {
-  const int C = (nitems + 7) >> 3;
-  if (!PERSIST) {
-    if (xcd) {
-      if (cursor < 0) return -1;
-      const int b = cursor;
-      cursor = -1;
-      const int it = (b & 7) * C + (b >> 3);
-      return it < nitems ? it : -1;
-    }
-    const int it = cursor;
-    cursor += gridDim.x;
-    return it < nitems ? it : -1;
+__device__ __forceinline__ ItemRange first_claim(int nitems, int claim, bool xcd) {
+  if (PERSIST) return ItemRange{0, 0};
+  const int b = (int)blockIdx.x;
+  if (xcd) {
+    const int C = (nitems + 7) >> 3;
+    const int c = b & 7, lo = c * C + (b >> 3) * claim;
+    return ItemRange{lo, min(min(lo + claim, c * C + C), nitems)};
   }
+  const int lo = b * claim;
+  return ItemRange{lo, min(lo + claim, nitems)};
+}
+
+// Next work item of this block, or -1 when there is none.  Non-persistent
+// blocks run their one claim.  Persistent launches (a fixed number of
+// blocks) pop claims from the shared queue, one atomic per claim, in list
+// order (finest level first), so blocks that draw cheap items come back for
+// more; with `xcd` a persistent block pops its own chunk first, then the
+// others.  Taking an item from the current claim involves no barrier (the
+// kernels end each item with one before LDS is reused); popping a claim
+// does, so every thread of the block must call this with the same range.
+template <bool PERSIST>
+__device__ __forceinline__ int next_item(ItemRange& r, int nitems, int claim, WorkQueue* q, int* s_claim, int* s_c,
+                                         bool xcd) {
+  if (r.next < r.end) return r.next++;
+  if (!PERSIST) return -1;
   if (threadIdx.x == 0) {
-    int res = -1;
+    int lo = -1, hi = -1;
     if (!xcd) {
-      const unsigned i = atomicAdd(&q->head[0], 1u);
-      if ((int)i < nitems) res = (int)i;
+      const int i = (int)atomicAdd(&q->head[0], (unsigned)claim);
+      if (i < nitems) {
+        lo = i;
+        hi = min(i + claim, nitems);
+      }
     } else {
-      while (res < 0 && *s_c < 8) {
+      const int C = (nitems + 7) >> 3;
+      while (lo < 0 && *s_c < 8) {
         const int c = (int)((blockIdx.x + *s_c) & 7);
-        const int lo = c * C, len = min(C, nitems - lo);
+        const int base = c * C, len = min(C, nitems - base);
         if (len > 0) {
-          const unsigned i = atomicAdd(&q->head[c], 1u);
-          if ((int)i < len) res = lo + (int)i;
+          const int i = (int)atomicAdd(&q->head[c], (unsigned)claim);
+          if (i < len) {
+            lo = base + i;
+            hi = base + min(i + claim, len);
+          }
         }
-        if (res < 0) ++*s_c;  // this chunk is drained: move to the next
+        if (lo < 0) ++*s_c;  // this chunk is drained: move to the next
       }
     }
-    *s_it = res;
+    s_claim[0] = lo;
+    s_claim[1] = hi;
   }
   __syncthreads();
-  const int it = *s_it;
+  const int lo = s_claim[0], hi = s_claim[1];
   __syncthreads();
-  return it;
+  if (lo < 0) return -1;
+  r.next = lo + 1;
+  r.end = hi;
+  return lo;
+}
+
+// Blocks of a non-persistent launch of nitems entries in claims of `claim`.
+inline int claim_blocks(int nitems, int claim, bool xcd) {
+  if (xcd) {
+    const int C = (nitems + 7) / 8;
+    return 8 * ((C + claim - 1) / claim);
+  }
+  return (nitems + claim - 1) / claim;
 }
 
 // Persistent launches leave the queue ready for the next one: the last block

@@ -47,7 +47,7 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     if (h->fused && !h->upwind_emf) {
       // one fused flux-update launch; the update's event pair measures zero
       launch_fused<T>(h->ndim, h->d_desc, h->d_xitems + L.fused.off, L.fused.n, s0, s1, parity, F, h->d_fmask, dt0, ph,
-                      h->d_err, h->d_queue, h->persistent_flux ? h->fused_pblocks : 0, h->xcd_chunks, s);
+                      h->d_err, h->d_queue, h->persistent_flux ? h->fused_pblocks : 0, h->xcd_chunks, h->claim, s);
       HIPCHK(hipGetLastError());
       if (timing) {
         HIPCHK(hipEventRecord(h->ev_pool[e1], s));
@@ -59,7 +59,8 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     }
   }
   launch_flux<T>(h->ndim, h->d_desc, h->d_fitems + L.flux.off, L.flux.n, s0, s1, parity, F, dt0, ph, h->d_err,
-                 h->d_queue, h->persistent_flux ? h->flux_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
+                 h->d_queue, h->persistent_flux ? h->flux_pblocks : 0, h->xcd_chunks, h->claim, h->upwind_emf,
+                 s);
   HIPCHK(hipGetLastError());
   if (timing) HIPCHK(hipEventRecord(h->ev_pool[e1], s));
   if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
@@ -69,7 +70,7 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
     }
   }
   launch_update<T>(h->ndim, h->d_desc, h->d_uitems + L.upd.off, L.upd.n, s0, s1, parity, F, dt0, ph, h->d_queue,
-                   h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, h->upwind_emf, s);
+                   h->persistent ? h->upd_pblocks : 0, h->xcd_chunks, h->claim, h->upwind_emf, s);
   HIPCHK(hipGetLastError());
   if (timing) {
     HIPCHK(hipEventRecord(h->ev_pool[e2], s));
@@ -674,7 +675,7 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
   if (zchunk) *zchunk = h->zchunk;
   if (launch_mode)
     *launch_mode = (h->persistent ? 1 : 0) | (h->xcd_chunks ? 2 : 0) | (h->persistent_flux && !h->persistent ? 4 : 0) |
-                 (h->fused ? 8 : 0);
+                 (h->fused ? 8 : 0) | ((h->claim == 8 ? 3 : h->claim / 2) << 4);
   return AMR_OK;
 }
 

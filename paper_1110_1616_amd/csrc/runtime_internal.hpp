@@ -159,6 +159,7 @@ struct amr_hierarchy {
   bool persistent = false;     // persistent launches popping d_queue, or one block per item
   bool persistent_flux = false;  // the flux kernel persistent (implied by `persistent`)
   bool xcd_chunks = false;     // item lists cut into one contiguous chunk per XCD
+  int claim = 1;               // work items a block takes at a time (launch mode bits 4-5)
   WorkQueue* d_queue = nullptr;
   int flux_pblocks = 0, upd_pblocks = 0;  // persistent grid sizes (resident blocks on the device)
   int device = 0;  // the device the tables live on (current at amr_create)

@@ -1051,8 +1051,9 @@ void set_update_zchunk(amr_hierarchy* h, int zchunk) {
 void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   if (policy != 0 && policy != 1) throw Error(AMR_EINVAL, "tile policy must be 0 or 1");
   if (zchunk < 1 || zchunk > 4096) throw Error(AMR_EINVAL, "z-chunk must be in [1, 4096]");
-  if (mode < 0 || mode > 15) throw Error(AMR_EINVAL, "launch mode must be in [0, 15]");
+  if (mode < 0 || mode > 63) throw Error(AMR_EINVAL, "launch mode must be in [0, 63]");
   h->persistent = (mode & 1) != 0;
+  h->claim = 1 << ((mode >> 4) & 3);
   h->persistent_flux = (mode & 5) != 0;
   h->xcd_chunks = (mode & 2) != 0;
   h->fused = (mode & 8) != 0;

@@ -141,7 +141,8 @@ def test_every_launch_configuration_gives_identical_results(key):
     only change how the same per-face and per-cell arithmetic is
     distributed: two coarse steps agree bit for bit under all 48
     configurations of the two-kernel path (each with one of the update
-    z-chunks 1, 2, 3, 8), and bit for bit among the 16 configurations of the
+    z-chunks 1, 2, 3, 8 and one of the claim sizes 1, 2, 4, 8), and bit for
+    bit among the 16 configurations of the
     fused flux-update kernel (launch mode bit 3) of one tile policy.  In
     FP64 the fused kernel's results move by an ulp here and there with the
     tile width and differ from the two-kernel path by as much (the same
@@ -154,10 +155,12 @@ def test_every_launch_configuration_gives_identical_results(key):
             for zi, zc in enumerate((8, 12, 16, 64)):
                 for per in (0, 1, 2, 3, 4, 6) if not fused else (8, 10, 12, 14):
                     uz = (1, 2, 3, 8)[(zi + per) % 4]
-                    log(f"case: launch config {key} policy={pol} zchunk={zc} mode={per} update zchunk={uz}")
+                    # work items per block claim: 1, 2, 4 or 8 (mode bits 4-5)
+                    mode = per | (((zi + pol + per) % 4) << 4)
+                    log(f"case: launch config {key} policy={pol} zchunk={zc} mode={mode} update zchunk={uz}")
                     H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
-                    H.set_launch_config(pol, zc, per, uz)
-                    assert A.amr_get_launch_config(H.h) == (pol, zc, per)
+                    H.set_launch_config(pol, zc, mode, uz)
+                    assert A.amr_get_launch_config(H.h) == (pol, zc, mode)
                     assert A.amr_get_update_zchunk(H.h) == uz
                     Ua, Ub = H.new_state(), H.new_state()
                     for gi, f in enumerate(fields):
@@ -186,7 +189,7 @@ def test_launch_configuration_rejects_bad_values():
     ndim, N0, L, grids, fields = _setup("3d")
     H = A.Hierarchy(ndim, N0, grids, nlevels=L, ghost=4)
     H.set_launch_config(1, 12, 6, 2)
-    for bad in ((2, 8, 0), (1, 0, 0), (1, 8, 16), (1, 8, -1)):
+    for bad in ((2, 8, 0), (1, 0, 0), (1, 8, 64), (1, 8, -1)):
         with pytest.raises(A.AmrError):
             A.amr_set_launch_config(H.h, *bad)
     with pytest.raises(A.AmrError):
@@ -196,8 +199,9 @@ def test_launch_configuration_rejects_bad_values():
 
 
 def test_autotune_keeps_the_state_and_the_results():
-    """The autotuner times all 80 launch configurations and then the update
-    z-chunks under the fastest, without changing what the next coarse step
+    """The autotuner times all 80 launch configurations, then the update
+    z-chunks under the fastest, then the claim sizes (work items per block
+    claim, launch mode bits 4-5), without changing what the next coarse step
     computes."""
     import torch
     ndim, N0, L, grids, fields = _setup("3d")
@@ -212,8 +216,11 @@ def test_autotune_keeps_the_state_and_the_results():
     assert 0 <= chosen < A.TUNE_CANDIDATES and all(t[3] > 0 for t in table)
     assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
     assert A.amr_get_update_zchunk(H.h) == table[chosen][4]
-    assert [t[4] for t in table[80:]] == [1, 2, 4, 8]
-    assert all(tuple(t[:3]) == tuple(table[80][:3]) for t in table[80:])
+    assert [t[4] for t in table[80:84]] == [1, 2, 4, 8]
+    assert all(tuple(t[:3]) == tuple(table[80][:3]) for t in table[80:84])
+    assert [t[2] >> 4 for t in table[84:]] == [1, 2, 3]
+    assert all(tuple(t[:2]) == tuple(table[80][:2]) and (t[2] & 15) == table[80][2] for t in table[84:])
+    assert len({t[4] for t in table[84:]}) == 1
     par = H.coarse_step(Ua, Ub, par, 0)
     torch.cuda.synchronize()
     got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]

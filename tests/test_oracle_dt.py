@@ -165,3 +165,27 @@ def test_flop_constants_match_oracle_counts():
         # the count per predicted cell still carries the primitive recovery
         # of the two outer band layers (a few flops per cell at these sizes)
         assert abs(per_pred - bench.FLOPS_PRED[ndim]) <= 0.005 * per_pred, (ndim, per_pred)
+
+
+def test_update_flop_constants_match_oracle_counts():
+    """The update's flop constants (the fused kernel's share of the roofline
+    numerator) decompose the oracle's own counts exactly: per updated cell,
+    per updated face-centred B component, and per edge EMF over the edges
+    the oracle forms (n + 2 along each edge in 3-D)."""
+    import ctypes as C
+
+    import bench
+
+    L = O.lib()
+    for ndim, sizes in ((3, (16, 24, 32)), (2, (32, 64, 128))):
+        for n in sizes:
+            out = np.zeros(8)
+            assert L.orc_count_step_flops(ndim, n, out.ctypes.data_as(C.POINTER(C.c_double))) == 0
+            cells = n ** ndim
+            faces = ndim * (n + 1) * n ** (ndim - 1)
+            edges = 3 * (n + 1) ** 2 * (n + 2) if ndim == 3 else (n + 1) ** 2
+            assert out[7] == bench.FLOPS_UPD_CELL[ndim] * cells + bench.FLOPS_UPD_FACE[ndim] * faces, (ndim, n)
+            assert out[6] == bench.FLOPS_EMF_EDGE * edges, (ndim, n)
+    # the per-launch count the bench uses: updated box n + 2 gv - 4
+    assert bench.update_flops(3, (8, 8, 8), 2) == 55 * 512 + 8 * 3 * 9 * 64 + 4 * 3 * 8 * 81
+    assert bench.update_flops(2, (8, 8), 4) == 48 * 144 + 5 * 2 * 13 * 12 + 4 * 169
