@@ -344,12 +344,11 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * takes 2^c consecutive work items at a time (grids per workgroup for grids
  * of one tile and one z-chunk; else a run of neighbouring tiles), for every
  * kernel of the launch.  launch_mode in [0, 63], else AMR_EINVAL; the claim
- * size never changes results.  The two-kernel configurations give bitwise identical
- * results, and so do the fused ones of one tile policy; in FP64 the fused
- * kernel differs from the two-kernel path, and between tile policies, by an
- * ulp here and there (the same expressions, compiled with different
- * multiply-add contraction; FP32 results agree bit for bit).  Changing tile_policy or zchunk rebuilds the work
- * lists and drops captured graphs.  Default: 1, 16, 0. */
+ * size never changes results.  Every configuration gives bitwise identical
+ * results (the device code contracts multiply-adds only inside a source
+ * expression, so an expression rounds the same way in every kernel).
+ * Changing tile_policy or zchunk rebuilds the work lists and drops captured
+ * graphs.  Default: 1, 16, 0. */
 amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
 

@@ -34,7 +34,11 @@ def build(verbose=False, jobs=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []
-    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    # -ffp-contract=on: multiply-adds are fused inside a source expression
+    # only (HIP's default also fuses across statements, wherever the code
+    # around an inlined helper allows), so every kernel rounds a shared
+    # expression the same way and all launch paths agree bit for bit
+    flags = ["--offload-arch=" + ARCH, "-O3", "-ffp-contract=on", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include")]
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")

@@ -16,9 +16,9 @@
 // rows (the last x- and y-face of the update region go to the lane that
 // holds them).  Every flux, EMF and update is formed with the same source
 // expressions as the two-kernel path (the update's arithmetic is shared, in
-// emf.hpp, without multiply-add contraction); in FP64 the compiler still
-// contracts a few operations of the predictor and the Riemann solver
-// differently here, so results agree with the two-kernel path to an ulp.
+// emf.hpp), and the library is compiled with multiply-add contraction
+// inside single expressions only, so the results equal the two-kernel
+// path's bit for bit.
 //
 // Face fluxes that the coarse/fine registers read afterwards are still
 // stored: a per-element mask marks them (bit d for the face normal to d) and
@@ -135,12 +135,27 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
     T fzp[5] = {T(0), T(0), T(0), T(0), T(0)};
     T exp_ = T(0), eyp_ = T(0), fy5p = T(0), fx6p = T(0);
 
-    if (NDIM == 3 && ook) load_prim_b<T, NDIM>(U, bx(cx, cy, kstart - 1), bx.sy, bx.sz, gm1, wprev);
 #pragma unroll
     for (int d = 0; d < 3; ++d) fbcur[d][0] = fbcur[d][1] = fbnext[d][0] = fbnext[d][1] = T(0);
-    if (ook) load_prim_faces_b<T, NDIM>(U, bx(cx, cy, kstart), bx.sy, bx.sz, gm1, wcur, fbcur);
-    if (NDIM == 3 && ook) load_prim_faces_b<T, NDIM>(U, bx(cx, cy, kstart + 1), bx.sy, bx.sz, gm1, wnext, fbnext);
-    if (rok) load_prim_b<T, NDIM>(U, bx(rcx, rcy, kstart), bx.sy, bx.sz, gm1, wring);
+    if (NDIM == 3) {
+      // the item's first planes: every load issued before any conversion
+      T r0[5], r1[5], r2[5], rr[5], f0[3][2], fr[3][2];
+      if (ook) {
+        load_raw3<T>(U, bx(cx, cy, kstart - 1), bx.sy, bx.sz, r0, f0);
+        load_raw3<T>(U, bx(cx, cy, kstart), bx.sy, bx.sz, r1, fbcur);
+        load_raw3<T>(U, bx(cx, cy, kstart + 1), bx.sy, bx.sz, r2, fbnext);
+      }
+      if (rok) load_raw3<T>(U, bx(rcx, rcy, kstart), bx.sy, bx.sz, rr, fr);
+      if (ook) {
+        raw3_to_prim<T>(r0, f0, gm1, wprev);
+        raw3_to_prim<T>(r1, fbcur, gm1, wcur);
+        raw3_to_prim<T>(r2, fbnext, gm1, wnext);
+      }
+      if (rok) raw3_to_prim<T>(rr, fr, gm1, wring);
+    } else {
+      if (ook) load_prim_faces_b<T, NDIM>(U, bx(cx, cy, kstart), bx.sy, bx.sz, gm1, wcur, fbcur);
+      if (rok) load_prim_b<T, NDIM>(U, bx(rcx, rcy, kstart), bx.sy, bx.sz, gm1, wring);
+    }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       if (live) sW[c][eo] = wcur[c];
