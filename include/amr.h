@@ -361,7 +361,7 @@ amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, i
 amr_status amr_set_update_zchunk(amr_hierarchy* h, int32_t zchunk);
 amr_status amr_get_update_zchunk(const amr_hierarchy* h, int32_t* zchunk);
 
-#define AMR_TUNE_CANDIDATES 87
+#define AMR_TUNE_CANDIDATES 107
 
 typedef struct {
   int32_t tile_policy, zchunk, launch_mode, update_zchunk;
@@ -370,14 +370,14 @@ typedef struct {
 
 /* Autotuner of the batched advance: fills every level's band (FULL, coarse
  * to fine) and computes dt0 (both redone by the next coarse step), then
- * times the 80 configurations tile_policy x zchunk in {8, 12, 16, 32} x
- * launch_mode in {0, 1, 2, 3, 4, 6, 8, 10, 12, 14} (entries 0..79, under the
+ * times the 100 configurations tile_policy x zchunk in {8, 12, 16, 24, 32} x
+ * launch_mode in {0, 1, 2, 3, 4, 6, 8, 10, 12, 14} (entries 0..99, under the
  * current update z-chunk), keeps the fastest, and under it times the update
- * z-chunks {1, 2, 4, 8} (entries 80..83) and then, under the kept update
+ * z-chunks {1, 2, 4, 8} (entries 100..103) and then, under the kept update
  * z-chunk, claims of 2, 4 and 8 items per block (launch mode bits 4-5,
- * entries 84..86), each over `reps` passes of every launch cycle's batched
+ * entries 104..106), each over `reps` passes of every launch cycle's batched
  * advance, reading each level's current buffer (parity) and writing the
- * other one, and keeps the fastest of all 87.  The state the
+ * other one, and keeps the fastest of all 107.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */

@@ -320,7 +320,7 @@ def amr_get_update_zchunk(h):
     return a.value
 
 
-TUNE_CANDIDATES = 87
+TUNE_CANDIDATES = 107
 
 
 def amr_autotune(h, Ua, Ub, parity, dt0, ws, reps=3):

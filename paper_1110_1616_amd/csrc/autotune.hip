@@ -42,12 +42,12 @@ int autotune(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t parity, do
     do_fill<T>(h, l, l > 0 ? AMR_FILL_FULL : AMR_FILL_SAME_LEVEL, cur, par, s);
   }
   do_dt<T>(h, Ua, Ub, parity, dt0, s);
-  const int zc[4] = {8, 12, 16, 32};
+  const int zc[5] = {8, 12, 16, 24, 32};
   const int modes[10] = {0, 1, 2, 3, 4, 6, 8, 10, 12, 14};
   int best = -1, n = 0, bpol = 1, bzc = 8, bmode = 0;
   double best_ms = 0.0;
   for (int pol = 0; pol < 2; ++pol)
-    for (int zi = 0; zi < 4; ++zi)
+    for (int zi = 0; zi < 5; ++zi)
       for (int mi = 0; mi < 10; ++mi, ++n) {
         set_launch_config(h, pol, zc[zi], modes[mi]);
         const double ms = time_cycles<T>(h, Ua, Ub, parity, dt0, ws, reps, s);

@@ -81,27 +81,41 @@ void run_list(amr_hierarchy* h, const LaunchList& L, const amr_state* Ua, const 
 
 // Registers written after level l stepped at its substep k: the coarse side
 // of the sync with level l+1 and the fine side (slot 1 + k mod R) of the sync
-// with level l-1.
+// with level l-1, queued as jobs of one batched register launch.
 template <class T>
-void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws, hipStream_t s) {
-  DevFlux<T> F = dflux<T>(h, ws);
+void flush_registers(amr_hierarchy* h, RegJobs<T>& jobs, const double* dt0, void* ws, hipStream_t s) {
+  launch_register_jobs<T>(h->ndim, h->d_desc, jobs, dflux<T>(h, ws), dt0, h->upwind_emf, s);
+  HIPCHK(hipGetLastError());
+  jobs.n = 0;
+  jobs.total = 0;
+}
+
+template <class T>
+void add_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws, RegJobs<T>& jobs, hipStream_t s) {
   const double div = (double)ipow(h->R, l);
-  if (l + 1 < h->nlev) {
-    const SyncTables& t = h->sync[l + 1];
+  auto add = [&](const SyncTables& t, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne, int slot) {
+    if (nf + ne <= 0) return;
+    if (jobs.n == kMaxRegJobs) flush_registers<T>(h, jobs, dt0, ws, s);
     T* freg = (T*)((char*)ws + t.reg_off);
     T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
-    launch_registers<T>(h->ndim, h->d_desc, t.d_freg_c, t.n_freg_c, t.d_ereg_c, t.n_ereg_c, F, freg, ereg, t.nfreg,
-                        t.nereg, 0, dt0, div, h->upwind_emf, s);
-    HIPCHK(hipGetLastError());
+    jobs.j[jobs.n++] = RegJob<T>{fe, ee, freg, ereg, nf, ne, t.nfreg, t.nereg, slot, jobs.total, div};
+    jobs.total += nf + ne;
+  };
+  if (l + 1 < h->nlev) {
+    const SyncTables& t = h->sync[l + 1];
+    add(t, t.d_freg_c, t.n_freg_c, t.d_ereg_c, t.n_ereg_c, 0);
   }
   if (l >= 1) {
     const SyncTables& t = h->sync[l];
-    T* freg = (T*)((char*)ws + t.reg_off);
-    T* ereg = (T*)((char*)ws + t.reg_off + ((int64_t)(1 + h->R) * t.nfreg * 6 * (int64_t)sizeof(T) + 255) / 256 * 256);
-    launch_registers<T>(h->ndim, h->d_desc, t.d_freg_f, t.n_freg_f, t.d_ereg_f, t.n_ereg_f, F, freg, ereg, t.nfreg,
-                        t.nereg, 1 + k % h->R, dt0, div, h->upwind_emf, s);
-    HIPCHK(hipGetLastError());
+    add(t, t.d_freg_f, t.n_freg_f, t.d_ereg_f, t.n_ereg_f, 1 + k % h->R);
   }
+}
+
+template <class T>
+void write_registers(amr_hierarchy* h, int l, int k, const double* dt0, void* ws, hipStream_t s) {
+  RegJobs<T> jobs;
+  add_registers<T>(h, l, k, dt0, ws, jobs, s);
+  flush_registers<T>(h, jobs, dt0, ws, s);
 }
 
 template <class T>
@@ -163,15 +177,18 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
         else do_fill<T>(h, l, AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s, step_band(h, l, k) == 2);
       }
       run_list<T>(h, lists[c], Ua, Ub, par, dt0, ws, s);
-      // levels whose window ends here: every grid has stepped; registers,
-      // then the level's buffers swap, then the synchronisations it closes
+      // levels whose window ends here: every grid has stepped; registers
+      // (one launch for all of them), then the level's buffers swap, then
+      // the synchronisations it closes
       uint32_t ending = 0;
+      RegJobs<T> jobs;
       for (int l = 0; l < L; ++l) {
         const int span = ipow(R, L - 1 - l);
         if ((c + 1) % span) continue;
         ending |= 1u << l;
-        write_registers<T>(h, l, c / span, dt0, ws, s);
+        add_registers<T>(h, l, c / span, dt0, ws, jobs, s);
       }
+      flush_registers<T>(h, jobs, dt0, ws, s);
       par ^= ending;
       for (int f = L - 1; f >= 1; --f)
         if ((c + 1) % ipow(R, L - f) == 0) do_sync<T>(h, f, cur(f), cur(f - 1), ws, s);

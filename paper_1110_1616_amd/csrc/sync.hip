@@ -71,28 +71,31 @@ __device__ __forceinline__ void reg_edge(const EdgeRegEntry& e, const GridDesc* 
   reg[(int64_t)slot * nreg + e.reg] = dt * (m / T(e.n));
 }
 
-// The face and edge registers of one fine step in one launch: threads
-// [0, nf) take face entries, [nf, nf + ne) edge entries.
+// The face and edge registers of every job of a launch cycle in one launch:
+// thread t takes entry t - begin of the job whose range holds it, face
+// entries first, then edge entries.
 template <class T, int NDIM, bool UPWIND>
-__global__ __launch_bounds__(256) void k_registers(const FaceRegEntry* __restrict__ fe, int nf,
-                                                   const EdgeRegEntry* __restrict__ ee, int ne,
-                                                   const GridDesc* __restrict__ grids, DevFlux<T> F,
-                                                   T* __restrict__ freg, int nfreg, T* __restrict__ ereg, int nereg,
-                                                   int slot, const double* __restrict__ dt0p, double dt_div) {
-  const T dt = T(dt0p[0] / dt_div);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nf + ne; t += gridDim.x * blockDim.x) {
-    if (t < nf) reg_face<T, NDIM>(fe[t], F, freg, nfreg, slot, dt);
-    else reg_edge<T, NDIM, UPWIND>(ee[t - nf], grids, F, ereg, nereg, slot, dt);
+__global__ __launch_bounds__(256) void k_registers(RegJobs<T> jobs, const GridDesc* __restrict__ grids, DevFlux<T> F,
+                                                   const double* __restrict__ dt0p) {
+  const double dt0 = dt0p[0];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < jobs.total; t += gridDim.x * blockDim.x) {
+    int j = 0;
+    while (j + 1 < jobs.n && t >= jobs.j[j + 1].begin) ++j;
+    const RegJob<T>& J = jobs.j[j];
+    const T dt = T(dt0 / J.dt_div);
+    const int i = t - J.begin;
+    if (i < J.nf) reg_face<T, NDIM>(J.fe[i], F, J.freg, J.nfreg, J.slot, dt);
+    else reg_edge<T, NDIM, UPWIND>(J.ee[i - J.nf], grids, F, J.ereg, J.nereg, J.slot, dt);
   }
 }
 
+// Reflux of one uncovered coarse cell.
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_reflux(const RefluxEntry* __restrict__ ent, int n, const T* __restrict__ reg,
-                                                int nreg, DevState<T> U) {
+__device__ __forceinline__ void reflux_one(const RefluxEntry& e, const T* __restrict__ reg, int nreg,
+                                           const DevState<T>& U) {
   constexpr int ns = NDIM == 2 ? 6 : 5;
   constexpr int imax = 6;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const RefluxEntry e = ent[t];
+  {
 #pragma unroll
     for (int q = 0; q < ns; ++q) {
       const int s = q < 5 ? q : 7;
@@ -124,12 +127,12 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxEntry* __restrict__ 
   }
 }
 
+// EMF correction of one copy of an uncovered coarse face.
 template <class T>
-__global__ __launch_bounds__(256) void k_emffix(const EmfFixEntry* __restrict__ ent, int n, const T* __restrict__ reg,
-                                                int nreg, DevState<T> U) {
+__device__ __forceinline__ void emffix_one(const EmfFixEntry& e, const T* __restrict__ reg, int nreg,
+                                           const DevState<T>& U) {
   constexpr int imax = 4;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const EmfFixEntry e = ent[t];
+  {
     T rc[imax], rf[imax][kR];
 #pragma unroll
     for (int i = 0; i < imax; ++i) {
@@ -156,12 +159,11 @@ __global__ __launch_bounds__(256) void k_emffix(const EmfFixEntry* __restrict__ 
   }
 }
 
+// Restriction of one covered coarse cell or coarse face copy.
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_restrict(const RestrictEntry* __restrict__ ent, int n,
-                                                  const GridDesc* __restrict__ grids, DevState<T> Uf,
-                                                  DevState<T> Uc) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const RestrictEntry e = ent[t];
+__device__ __forceinline__ void restrict_one(const RestrictEntry& e, const GridDesc* __restrict__ grids,
+                                             const DevState<T>& Uf, const DevState<T>& Uc) {
+  {
     const GridDesc G = grids[e.fgrid];
     const int64_t st[3] = {1, G.P[0], (int64_t)G.P[0] * G.P[1]};
     if (e.d < 0) {
@@ -208,16 +210,32 @@ __global__ __launch_bounds__(256) void k_restrict(const RestrictEntry* __restric
   }
 }
 
+// One synchronisation in one launch: threads [0, nr) reflux uncovered
+// coarse cells, the next ne correct uncovered coarse faces, the rest
+// restrict covered cells and faces.  The three sets of outputs are disjoint
+// and none reads another's outputs, so the order inside the launch is free.
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_sync(const RefluxEntry* __restrict__ rfx, int nr,
+                                              const EmfFixEntry* __restrict__ efx, int ne,
+                                              const RestrictEntry* __restrict__ rst, int nrs,
+                                              const GridDesc* __restrict__ grids, const T* __restrict__ freg,
+                                              int nfreg, const T* __restrict__ ereg, int nereg, DevState<T> Uf,
+                                              DevState<T> Uc) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nr + ne + nrs; t += gridDim.x * blockDim.x) {
+    if (t < nr) reflux_one<T, NDIM>(rfx[t], freg, nfreg, Uc);
+    else if (t < nr + ne) emffix_one<T>(efx[t - nr], ereg, nereg, Uc);
+    else restrict_one<T, NDIM>(rst[t - nr - ne], grids, Uf, Uc);
+  }
+}
+
 }  // namespace
 
 template <class T>
-void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
-                      DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
-                      double dt_div, bool upwind_emf, hipStream_t s) {
-  if (nf + ne <= 0) return;
-#define AMR_REGS(ND, U)                                                                                            \
-  hipLaunchKernelGGL((k_registers<T, ND, U>), dim3(blocks_for((int64_t)nf + ne)), dim3(256), 0, s, fe, nf, ee, ne, \
-                     grids, F, freg, nfreg, ereg, nereg, slot, dt0, dt_div)
+void launch_register_jobs(int ndim, const GridDesc* grids, const RegJobs<T>& jobs, DevFlux<T> F, const double* dt0,
+                          bool upwind_emf, hipStream_t s) {
+  if (jobs.total <= 0) return;
+#define AMR_REGS(ND, U) \
+  hipLaunchKernelGGL((k_registers<T, ND, U>), dim3(blocks_for(jobs.total)), dim3(256), 0, s, jobs, grids, F, dt0)
   if (ndim == 3) {
     if (upwind_emf) AMR_REGS(3, true);
     else AMR_REGS(3, false);
@@ -232,33 +250,20 @@ template <class T>
 void launch_sync(int ndim, int R, const GridDesc* grids, const SyncTables& t, const T* freg, const T* ereg,
                  DevState<T> Uf, DevState<T> Uc, hipStream_t s) {
   (void)R;  // the kernels are unrolled over kR; the caller checks R == kR
-  if (t.n_reflux > 0) {
-    if (ndim == 3)
-      hipLaunchKernelGGL((k_reflux<T, 3>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
-                         t.nfreg, Uc);
-    else
-      hipLaunchKernelGGL((k_reflux<T, 2>), dim3(blocks_for(t.n_reflux)), dim3(256), 0, s, t.d_reflux, t.n_reflux, freg,
-                         t.nfreg, Uc);
-  }
-  if (t.n_emffix > 0)
-    hipLaunchKernelGGL((k_emffix<T>), dim3(blocks_for(t.n_emffix)), dim3(256), 0, s, t.d_emffix, t.n_emffix, ereg,
-                       t.nereg, Uc);
-  if (t.n_restrict > 0) {
-    if (ndim == 3)
-      hipLaunchKernelGGL((k_restrict<T, 3>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
-                         t.n_restrict, grids, Uf, Uc);
-    else
-      hipLaunchKernelGGL((k_restrict<T, 2>), dim3(blocks_for(t.n_restrict)), dim3(256), 0, s, t.d_restrict,
-                         t.n_restrict, grids, Uf, Uc);
-  }
+  const int n = t.n_reflux + t.n_emffix + t.n_restrict;
+  if (n <= 0) return;
+#define AMR_SYNC(ND)                                                                                              \
+  hipLaunchKernelGGL((k_sync<T, ND>), dim3(blocks_for(n)), dim3(256), 0, s, t.d_reflux, t.n_reflux, t.d_emffix,   \
+                     t.n_emffix, t.d_restrict, t.n_restrict, grids, freg, t.nfreg, ereg, t.nereg, Uf, Uc)
+  if (ndim == 3) AMR_SYNC(3);
+  else AMR_SYNC(2);
+#undef AMR_SYNC
 }
 
-template void launch_registers<float>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
-                                      DevFlux<float>, float*, float*, int, int, int, const double*, double, bool,
-                                      hipStream_t);
-template void launch_registers<double>(int, const GridDesc*, const FaceRegEntry*, int, const EdgeRegEntry*, int,
-                                       DevFlux<double>, double*, double*, int, int, int, const double*, double, bool,
-                                       hipStream_t);
+template void launch_register_jobs<float>(int, const GridDesc*, const RegJobs<float>&, DevFlux<float>,
+                                          const double*, bool, hipStream_t);
+template void launch_register_jobs<double>(int, const GridDesc*, const RegJobs<double>&, DevFlux<double>,
+                                           const double*, bool, hipStream_t);
 template void launch_sync<float>(int, int, const GridDesc*, const SyncTables&, const float*, const float*,
                                  DevState<float>, DevState<float>, hipStream_t);
 template void launch_sync<double>(int, int, const GridDesc*, const SyncTables&, const double*, const double*,

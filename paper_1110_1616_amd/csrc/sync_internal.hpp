@@ -67,12 +67,27 @@ struct SyncTables {
   }
 };
 
-// Write registers of one side (slot 0: coarse, slot 1..R: fine substep) from
-// the face fluxes of the launch that just ran.
+// Register writes of one side of one sync (slot 0: coarse, slot 1..R: fine
+// substep) from the face fluxes of the launch that just ran; the table of
+// entries [begin, begin + nf + ne) of a batched launch.
+template <class T> struct RegJob {
+  const FaceRegEntry* fe;
+  const EdgeRegEntry* ee;
+  T* freg;
+  T* ereg;
+  int nf, ne, nfreg, nereg, slot, begin;
+  double dt_div;  // level l steps dt0 / R^l
+};
+// Every register write that follows one launch cycle (the levels whose step
+// window ends there, both sides of each of their syncs): one kernel launch.
+constexpr int kMaxRegJobs = 16;
+template <class T> struct RegJobs {
+  RegJob<T> j[kMaxRegJobs];
+  int n = 0, total = 0;
+};
 template <class T>
-void launch_registers(int ndim, const GridDesc* grids, const FaceRegEntry* fe, int nf, const EdgeRegEntry* ee, int ne,
-                      DevFlux<T> F, T* freg, T* ereg, int nfreg, int nereg, int slot, const double* dt0,
-                      double dt_div, bool upwind_emf, hipStream_t s);
+void launch_register_jobs(int ndim, const GridDesc* grids, const RegJobs<T>& jobs, DevFlux<T> F, const double* dt0,
+                          bool upwind_emf, hipStream_t s);
 
 // Reflux, EMF fix (coarse level state Uc) and restriction (fine Uf -> Uc).
 template <class T>

@@ -190,7 +190,7 @@ def test_launch_configuration_rejects_bad_values():
 
 
 def test_autotune_keeps_the_state_and_the_results():
-    """The autotuner times all 80 launch configurations, then the update
+    """The autotuner times all 100 launch configurations, then the update
     z-chunks under the fastest, then the claim sizes (work items per block
     claim, launch mode bits 4-5), without changing what the next coarse step
     computes."""
@@ -207,11 +207,12 @@ def test_autotune_keeps_the_state_and_the_results():
     assert 0 <= chosen < A.TUNE_CANDIDATES and all(t[3] > 0 for t in table)
     assert A.amr_get_launch_config(H.h) == tuple(table[chosen][:3])
     assert A.amr_get_update_zchunk(H.h) == table[chosen][4]
-    assert [t[4] for t in table[80:84]] == [1, 2, 4, 8]
-    assert all(tuple(t[:3]) == tuple(table[80][:3]) for t in table[80:84])
-    assert [t[2] >> 4 for t in table[84:]] == [1, 2, 3]
-    assert all(tuple(t[:2]) == tuple(table[80][:2]) and (t[2] & 15) == table[80][2] for t in table[84:])
-    assert len({t[4] for t in table[84:]}) == 1
+    assert [t[4] for t in table[100:104]] == [1, 2, 4, 8]
+    assert all(tuple(t[:3]) == tuple(table[100][:3]) for t in table[100:104])
+    assert [t[2] >> 4 for t in table[104:]] == [1, 2, 3]
+    assert all(tuple(t[:2]) == tuple(table[100][:2]) and (t[2] & 15) == table[100][2] for t in table[104:])
+    assert len({t[4] for t in table[104:]}) == 1
+    assert sorted({t[1] for t in table[:100]}) == [8, 12, 16, 24, 32]
     par = H.coarse_step(Ua, Ub, par, 0)
     torch.cuda.synchronize()
     got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
