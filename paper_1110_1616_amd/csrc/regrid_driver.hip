@@ -294,6 +294,7 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
   auto one = [&](size_t t) {
     const int gi = lg[t];
     Per& m = per[t];
+    LevelIndex::Memo omemo, pmemo;  // lookups on the old level and the new parent level
     const amr_grid& GG = hn->grids[gi];
     const GridDesc& G = hn->desc[gi];
     int n[3] = {1, 1, 1};
@@ -307,7 +308,7 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
         int w[3] = {p[0], p[1], p[2]};
         if (cand == 1) w[cls - 1] -= 1;
         if (!OI.wrap(w)) continue;
-        const int og = OI.find_cell(w);
+        const int og = OI.find_cell(w, omemo);
         if (og < 0) continue;
         if (best < 0 || og < best) {
           best = og;
@@ -340,7 +341,7 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
             if (cls == 0) {
               int cc[3] = {floordiv(p[0], 2), floordiv(p[1], 2), nd == 3 ? floordiv(p[2], 2) : 0};
               if (!PI.wrap(cc)) throw Error(AMR_EINVAL, "overlap: prolongation source outside the domain");
-              const int pg = PI.find_cell(cc);
+              const int pg = PI.find_cell(cc, pmemo);
               if (pg < 0) throw Error(AMR_EINVAL, "overlap: new cell has no parent");
               const GridDesc& P = hn->desc[pg];
               const amr_grid& PG = hn->grids[pg];
@@ -359,12 +360,12 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
             for (int a = 0; a < 3; ++a) cc[a] = a < nd ? floordiv(p[a], 2) : 0;
             int w[3] = {cc[0], cc[1], cc[2]};
             int pg = -1;
-            if (PI.wrap(w)) pg = PI.find_cell(w);
+            if (PI.wrap(w)) pg = PI.find_cell(w, pmemo);
             if (pg < 0) {
               int w2[3] = {cc[0], cc[1], cc[2]};
               w2[d] -= 1;
               if (PI.wrap(w2)) {
-                pg = PI.find_cell(w2);
+                pg = PI.find_cell(w2, pmemo);
                 if (pg >= 0) {
                   w[0] = w2[0];
                   w[1] = w2[1];
@@ -398,7 +399,7 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
         for (int i = 0; i < n[0] / 2; ++i) {
           const int loc[3] = {2 * i, 2 * j, nd == 3 ? 2 * k : 0};
           int w[3] = {GG.lo[0] + loc[0], GG.lo[1] + loc[1], GG.lo[2] + loc[2]};
-          if (OI.wrap(w) && OI.find_cell(w) >= 0) continue;  // copied coarse cell
+          if (OI.wrap(w) && OI.find_cell(w, omemo) >= 0) continue;  // copied coarse cell
           m.pj.push_back(ProjEntry{gi, (int32_t)elem(G, nd, loc[0], loc[1], loc[2])});
         }
   };

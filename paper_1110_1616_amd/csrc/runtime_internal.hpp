@@ -259,23 +259,29 @@ struct LevelIndex {
     return true;
   }
   // Grid whose interior holds cell c (already wrapped), or -1.  Lookups come
-  // in runs from one grid, so each thread first tries its last two hits (the
-  // grids of a level are disjoint: a grid of this level holding c is the
-  // answer, whatever lookup produced it).
-  int find_cell(const int (&c)[3]) const {
-    thread_local int memo[2] = {-1, -1};
-    thread_local unsigned turn = 0;
-    for (int m = 0; m < 2; ++m)
-      if (holds(memo[m], c)) return memo[m];
+  // in runs from a few grids, so the caller's memo keeps the last eight hits,
+  // tried first (the grids of a level are disjoint: a grid of this level
+  // holding c is the answer, whatever lookup produced it).
+  struct Memo {
+    int g[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    unsigned turn = 0;
+  };
+  int find_cell(const int (&c)[3], Memo& memo) const {
+    for (int m = 0; m < 8; ++m)
+      if (holds(memo.g[m], c)) return memo.g[m];
     auto it = buckets.find(key(floordiv(c[0], B), floordiv(c[1], B), floordiv(c[2], B)));
     if (it == buckets.end()) return -1;
     for (int gi : it->second) {
       if (holds(gi, c)) {
-        memo[turn++ & 1] = gi;
+        memo.g[memo.turn++ & 7] = gi;
         return gi;
       }
     }
     return -1;
+  }
+  int find_cell(const int (&c)[3]) const {
+    Memo m;
+    return find_cell(c, m);
   }
 };
 

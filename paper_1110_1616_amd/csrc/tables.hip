@@ -390,6 +390,7 @@ void build_fill_maps(amr_hierarchy* h) {
     std::vector<GridMaps> per(lg.size());
     auto one_grid = [&](size_t slot) {
     const int gi = lg[slot];
+    LevelIndex::Memo same, par;  // lookups of this grid's band on its level and the parent's
     std::vector<CopyEntry>(&cp)[4] = per[slot].cp;
     std::vector<CopyEntry>(&cp2)[4] = per[slot].cp2;
     std::vector<ProlongEntry>& pc = per[slot].pc;
@@ -427,7 +428,7 @@ void build_fill_maps(amr_hierarchy* h) {
                 if (cand == 1) c[cls - 1] -= 1;
                 int w[3] = {c[0], c[1], c[2]};
                 if (!LI.wrap(w)) continue;
-                int s = LI.find_cell(w);
+                int s = LI.find_cell(w, same);
                 if (s < 0) continue;
                 // the element itself, in the wrapped frame of grid s
                 int e[3] = {w[0], w[1], w[2]};
@@ -438,7 +439,7 @@ void build_fill_maps(amr_hierarchy* h) {
                   c2[cls - 1] -= 1;
                   int w2[3] = {c2[0], c2[1], c2[2]};
                   if (LI.wrap(w2)) {
-                    int s2 = LI.find_cell(w2);
+                    int s2 = LI.find_cell(w2, same);
                     if (s2 >= 0 && s2 < s) {
                       s = s2;
                       e[0] = w2[0];
@@ -481,7 +482,7 @@ void build_fill_maps(amr_hierarchy* h) {
               if (cls == 0) {
                 int cc[3] = {floordiv(gpos[0], 2), floordiv(gpos[1], 2), nd == 3 ? floordiv(gpos[2], 2) : 0};
                 if (!PI.wrap(cc)) throw Error(AMR_EINVAL, "prolongation source outside the domain");
-                int pg = PI.find_cell(cc);
+                int pg = PI.find_cell(cc, par);
                 if (pg < 0) throw Error(AMR_EINVAL, "proper nesting violated: band cell has no parent");
                 const GridDesc& P = h->desc[pg];
                 const amr_grid& PG = h->grids[pg];
@@ -502,12 +503,12 @@ void build_fill_maps(amr_hierarchy* h) {
                 // pick the coarse cell on its high side if covered, else low
                 int w[3] = {cc[0], cc[1], cc[2]};
                 int pg = -1;
-                if (PI.wrap(w)) pg = PI.find_cell(w);
+                if (PI.wrap(w)) pg = PI.find_cell(w, par);
                 if (!mid && pg < 0) {
                   int w2[3] = {cc[0], cc[1], cc[2]};
                   w2[d] -= 1;
                   if (PI.wrap(w2)) {
-                    pg = PI.find_cell(w2);
+                    pg = PI.find_cell(w2, par);
                     if (pg >= 0) {
                       w[0] = w2[0];
                       w[1] = w2[1];
@@ -536,45 +537,36 @@ void build_fill_maps(amr_hierarchy* h) {
     };
     parallel_for(lg.size(), one_grid);
     // concatenate: copies class by class (cells, x-, y-, z-faces), each in
-    // grid order; prolongations in grid order
-    size_t ncp[4] = {0, 0, 0, 0}, npc = 0, npf = 0;
-    for (const GridMaps& m : per) {
-      for (int c = 0; c < 4; ++c) ncp[c] += m.cp[c].size();
-      npc += m.pc.size();
-      npf += m.pf.size();
+    // grid order; prolongations in grid order.  Every grid's lists go to
+    // offsets known in advance, copied (and freed) by the worker threads.
+    const size_t ng = per.size();
+    std::vector<size_t> o1(4 * ng + 1, 0), o2(4 * ng + 1, 0), opc(ng + 1, 0), opf(ng + 1, 0);
+    for (int c = 0; c < 4; ++c)
+      for (size_t g = 0; g < ng; ++g) {
+        o1[c * ng + g + 1] = o1[c * ng + g] + per[g].cp[c].size();
+        o2[c * ng + g + 1] = o2[c * ng + g] + per[g].cp2[c].size();
+      }
+    for (size_t g = 0; g < ng; ++g) {
+      opc[g + 1] = opc[g] + per[g].pc.size();
+      opf[g + 1] = opf[g] + per[g].pf.size();
     }
-    std::vector<CopyEntry> all;
-    all.reserve(ncp[0] + ncp[1] + ncp[2] + ncp[3]);
-    int4 cls = make_int4(0, 0, 0, 0);
-    for (int c = 0; c < 4; ++c) {
-      for (const GridMaps& m : per) all.insert(all.end(), m.cp[c].begin(), m.cp[c].end());
-      int v = (int)all.size();
-      if (c == 0) cls.x = v;
-      if (c == 1) cls.y = v;
-      if (c == 2) cls.z = v;
-      if (c == 3) cls.w = v;
-    }
-    std::vector<CopyEntry> all2;
-    int4 cls2 = make_int4(0, 0, 0, 0);
-    for (int c = 0; c < 4; ++c) {
-      for (const GridMaps& m : per) all2.insert(all2.end(), m.cp2[c].begin(), m.cp2[c].end());
-      int v = (int)all2.size();
-      if (c == 0) cls2.x = v;
-      if (c == 1) cls2.y = v;
-      if (c == 2) cls2.z = v;
-      if (c == 3) cls2.w = v;
-    }
+    std::vector<CopyEntry> all(o1[4 * ng]), all2(o2[4 * ng]);
+    std::vector<ProlongEntry> pc(opc[ng]), pf(opf[ng]);
+    parallel_for(ng, [&](size_t g) {
+      GridMaps& m = per[g];
+      for (int c = 0; c < 4; ++c) {
+        std::copy(m.cp[c].begin(), m.cp[c].end(), all.begin() + o1[c * ng + g]);
+        std::copy(m.cp2[c].begin(), m.cp2[c].end(), all2.begin() + o2[c * ng + g]);
+      }
+      std::copy(m.pc.begin(), m.pc.end(), pc.begin() + opc[g]);
+      std::copy(m.pf.begin(), m.pf.end(), pf.begin() + opf[g]);
+      m = GridMaps();
+    });
+    const int4 cls = make_int4((int)o1[ng], (int)o1[2 * ng], (int)o1[3 * ng], (int)o1[4 * ng]);
+    const int4 cls2 = make_int4((int)o2[ng], (int)o2[2 * ng], (int)o2[3 * ng], (int)o2[4 * ng]);
     h->copy2_cls[l] = cls2;
     h->n_copy2[l] = (int)all2.size();
     h->d_copy2[l] = dev_upload(all2);
-    std::vector<ProlongEntry> pc, pf;
-    pc.reserve(npc);
-    pf.reserve(npf);
-    for (GridMaps& m : per) {
-      pc.insert(pc.end(), m.pc.begin(), m.pc.end());
-      pf.insert(pf.end(), m.pf.begin(), m.pf.end());
-      m = GridMaps();
-    }
     h->copy_cls[l] = cls;
     h->n_copy[l] = (int)all.size();
     h->d_copy[l] = dev_upload(all);
@@ -599,11 +591,12 @@ void check_nesting(amr_hierarchy* h) {
         lo[a] = a < nd ? G.lo[a] / h->R - buf : 0;
         hi[a] = a < nd ? G.hi[a] / h->R + buf : 1;
       }
+      LevelIndex::Memo memo;
       for (int k = lo[2]; k < hi[2]; ++k)
         for (int j = lo[1]; j < hi[1]; ++j)
           for (int i = lo[0]; i < hi[0]; ++i) {
             int c[3] = {i, j, k};
-            if (!PI.wrap(c) || PI.find_cell(c) < 0)
+            if (!PI.wrap(c) || PI.find_cell(c, memo) < 0)
               throw Error(AMR_EINVAL, "grid " + std::to_string(gi) + " violates proper nesting");
           }
     }
@@ -631,6 +624,8 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   LevelIndex CI, FI;
   CI.build(h, c);
   FI.build(h, f);
+  for (int a = 0; a < nd; ++a)
+    if (CI.N[a] >= (1 << 20)) throw Error(AMR_EUNSUPPORTED, "level exceeds 2^20 cells along an axis");
   // covered(p) for coarse cells p of the current coarse grid's box grown by
   // one cell: a mask filled from the fine grids' boxes (and their periodic
   // images) before the grid's elements are visited
@@ -705,11 +700,12 @@ void build_sync_tables(amr_hierarchy* h, int f) {
         }
   };
   // fine grid owning fine cell p (unwrapped); shift = wrap(p) - p
+  LevelIndex::Memo fmemo;
   auto fine_owner = [&](const int (&p)[3], int (&shift)[3]) {
     int w[3] = {p[0], p[1], p[2]};
     if (!FI.wrap(w)) return -1;
     for (int a = 0; a < 3; ++a) shift[a] = w[a] - p[a];
-    return FI.find_cell(w);
+    return FI.find_cell(w, fmemo);
   };
   const double dxc[3] = {h->p.dx0[0] / ipow(R, c), h->p.dx0[1] / ipow(R, c), nd == 3 ? h->p.dx0[2] / ipow(R, c) : 1.0};
   SyncTables& T = h->sync[f];
@@ -718,7 +714,12 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   std::vector<RefluxEntry> rfx;
   std::vector<EmfFixEntry> efx;
   std::vector<RestrictEntry> rst;
-  std::map<std::vector<int>, int> edge_id;
+  // edge registers deduplicated by (axis, wrapped edge index): the key packs
+  // the axis and three coordinates below 2^20 each
+  std::unordered_map<int64_t, int> edge_id;
+  auto edge_key = [](int a, const int (&w)[3]) {
+    return (((int64_t)a << 60) | ((int64_t)w[2] << 40) | ((int64_t)w[1] << 20) | (int64_t)w[0]);
+  };
   int nfreg = 0;
 
   for (int gi : h->level_grids[c]) {
@@ -865,7 +866,7 @@ void build_sync_tables(amr_hierarchy* h, int f) {
                 // dedupe registers by (axis, wrapped edge index)
                 int w[3] = {e[0], e[1], e[2]};
                 for (int a = 0; a < nd; ++a) w[a] = posmod(w[a], CI.N[a]);
-                std::vector<int> key = {ea, w[0], w[1], w[2]};
+                const int64_t key = edge_key(ea, w);
                 int re;
                 auto it = edge_id.find(key);
                 if (it == edge_id.end()) {
