@@ -19,9 +19,8 @@ namespace {
 // ------------------------------------------------------------------ copies
 // entries [0, nc[0]) cells, then x-, y-, z-face entries.
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_copy(const CopyEntry* __restrict__ ent, int n, int4 cls, DevState<T> U) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const CopyEntry e = ent[t];
+__device__ __forceinline__ void copy_one(int t, const CopyEntry& e, int4 cls, const DevState<T>& U) {
+  {
     if (t < cls.x) {
       U.f[0][e.dst] = U.f[0][e.src];
       U.f[1][e.dst] = U.f[1][e.src];
@@ -43,11 +42,9 @@ __global__ __launch_bounds__(256) void k_copy(const CopyEntry* __restrict__ ent,
 // Cells: U_f = U_c + sum_d (s_d / 4) minmod(U_c - U_{c-e_d}, U_{c+e_d} - U_c)
 // for the conserved cell fields (R = 2, s_d = +-1 the fine half).
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_prolong_cells(const ProlongEntry* __restrict__ ent, int n,
-                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
-                                                       DevState<T> Ud) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const ProlongEntry e = ent[t];
+__device__ __forceinline__ void prolong_cell_one(const ProlongEntry& e, const GridDesc* __restrict__ grids,
+                                                 const DevState<T>& Us, const DevState<T>& Ud) {
+  {
     const GridDesc P = grids[e.pgrid];
     const int64_t st[3] = {1, P.P[0], (int64_t)P.P[0] * P.P[1]};
     const int nfield = NDIM == 2 ? 6 : 5;
@@ -81,11 +78,9 @@ __device__ __forceinline__ T tslope(const T* f, int64_t e, int64_t s) {
 }
 
 template <class T, int NDIM>
-__global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __restrict__ ent, int n,
-                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
-                                                       DevState<T> Ud, Phys ph) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const ProlongEntry e = ent[t];
+__device__ __forceinline__ void prolong_face_one(const ProlongEntry& e, const GridDesc* __restrict__ grids,
+                                                 const DevState<T>& Us, const DevState<T>& Ud, const Phys& ph) {
+  {
     const GridDesc P = grids[e.pgrid];
     const int64_t st[3] = {1, P.P[0], (int64_t)P.P[0] * P.P[1]};
     const int d = e.code & 3;
@@ -126,6 +121,45 @@ __global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __res
       v = a0 + T(0.5) * s1 * ay + T(0.5) * s2 * az;
     }
     Ud.f[5 + d][e.dst] = v;
+  }
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_copy(const CopyEntry* __restrict__ ent, int n, int4 cls, DevState<T> U) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) copy_one<T, NDIM>(t, ent[t], cls, U);
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_prolong_cells(const ProlongEntry* __restrict__ ent, int n,
+                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
+                                                       DevState<T> Ud) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    prolong_cell_one<T, NDIM>(ent[t], grids, Us, Ud);
+}
+
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_prolong_faces(const ProlongEntry* __restrict__ ent, int n,
+                                                       const GridDesc* __restrict__ grids, DevState<T> Us,
+                                                       DevState<T> Ud, Phys ph) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    prolong_face_one<T, NDIM>(ent[t], grids, Us, Ud, ph);
+}
+
+// A full band fill in one launch: threads [0, nc) copy same-level band
+// elements, the next npc prolong band cells from the parent level, the rest
+// band faces.  The three write disjoint band elements, the copies read the
+// level's interiors and the prolongations the parent level only, so the
+// order inside the launch is free.
+template <class T, int NDIM>
+__global__ __launch_bounds__(256) void k_fill(const CopyEntry* __restrict__ cp, int nc, int4 cls,
+                                              const ProlongEntry* __restrict__ pc, int npc,
+                                              const ProlongEntry* __restrict__ pf, int npf,
+                                              const GridDesc* __restrict__ grids, DevState<T> Us, DevState<T> Ud,
+                                              Phys ph) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nc + npc + npf; t += gridDim.x * blockDim.x) {
+    if (t < nc) copy_one<T, NDIM>(t, cp[t], cls, Ud);
+    else if (t < nc + npc) prolong_cell_one<T, NDIM>(pc[t - nc], grids, Us, Ud);
+    else prolong_face_one<T, NDIM>(pf[t - nc - npc], grids, Us, Ud, ph);
   }
 }
 
@@ -313,6 +347,20 @@ void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const Prolo
   }
 }
 
+template <class T>
+void launch_fill_full(int ndim, const CopyEntry* cp, int nc, int4 cls, const ProlongEntry* cells, int ncells,
+                      const ProlongEntry* faces, int nfaces, const GridDesc* grids, DevState<T> Us, DevState<T> Ud,
+                      Phys ph, hipStream_t s) {
+  const int64_t n = (int64_t)nc + ncells + nfaces;
+  if (n <= 0) return;
+  if (ndim == 3)
+    hipLaunchKernelGGL((k_fill<T, 3>), dim3(blocks_for(n)), dim3(256), 0, s, cp, nc, cls, cells, ncells, faces, nfaces,
+                       grids, Us, Ud, ph);
+  else
+    hipLaunchKernelGGL((k_fill<T, 2>), dim3(blocks_for(n)), dim3(256), 0, s, cp, nc, cls, cells, ncells, faces, nfaces,
+                       grids, Us, Ud, ph);
+}
+
 constexpr int kCflBlocks = 2048;  // 8 per CU on 256 CUs
 
 template <class T>
@@ -357,6 +405,9 @@ void launch_store(int ndim, const GridDesc& G, DevState<T> U, double* const* out
   template void launch_copy<T>(int, const CopyEntry*, int, int4, DevState<T>, hipStream_t);                       \
   template void launch_prolong<T>(int, const ProlongEntry*, int, const ProlongEntry*, int, const GridDesc*,       \
                                   DevState<T>, DevState<T>, Phys, hipStream_t);                                   \
+  template void launch_fill_full<T>(int, const CopyEntry*, int, int4, const ProlongEntry*, int,                   \
+                                    const ProlongEntry*, int, const GridDesc*, DevState<T>, DevState<T>, Phys,    \
+                                    hipStream_t);                                                                 \
   template void launch_cfl<T>(int, const GridDesc*, const int4*, int, DevState<T>, DevState<T>, uint32_t, Phys,   \
                               unsigned long long*, ErrBlock*, double, double*, hipStream_t);                      \
   template void launch_load_prim<T>(int, const GridDesc&, const double* const*, const double* const*,            \

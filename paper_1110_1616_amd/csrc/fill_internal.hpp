@@ -23,6 +23,11 @@ struct ProlongEntry {
 
 template <class T>
 void launch_copy(int ndim, const CopyEntry* ent, int n, int4 cls, DevState<T> U, hipStream_t s);
+// A full band fill (the copies and both prolongations) in one launch.
+template <class T>
+void launch_fill_full(int ndim, const CopyEntry* cp, int nc, int4 cls, const ProlongEntry* cells, int ncells,
+                      const ProlongEntry* faces, int nfaces, const GridDesc* grids, DevState<T> Us, DevState<T> Ud,
+                      Phys ph, hipStream_t s);
 // Prolongation reads the parent level from Us and writes the band into Ud.
 template <class T>
 void launch_prolong(int ndim, const ProlongEntry* cells, int ncells, const ProlongEntry* faces, int nfaces,

@@ -134,11 +134,15 @@ void do_sync(amr_hierarchy* h, int f, const amr_state* Uf, amr_state* Uc, void* 
 template <class T>
 void do_fill(amr_hierarchy* h, int level, int mode, amr_state* Ul, const amr_state* Up, hipStream_t s,
              bool band2_only) {
-  if (band2_only)
+  if (mode == AMR_FILL_FULL && level > 0 && !band2_only)
+    launch_fill_full<T>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], h->d_pcell[level],
+                        h->n_pcell[level], h->d_pface[level], h->n_pface[level], h->d_desc, dstate<T>(Up),
+                        dstate<T>(Ul), phys(h), s);
+  else if (band2_only)
     launch_copy<T>(h->ndim, h->d_copy2[level], h->n_copy2[level], h->copy2_cls[level], dstate<T>(Ul), s);
   else
     launch_copy<T>(h->ndim, h->d_copy[level], h->n_copy[level], h->copy_cls[level], dstate<T>(Ul), s);
-  if (mode == AMR_FILL_FULL && level > 0)
+  if (mode == AMR_FILL_FULL && level > 0 && band2_only)
     launch_prolong<T>(h->ndim, h->d_pcell[level], h->n_pcell[level], h->d_pface[level], h->n_pface[level], h->d_desc,
                       dstate<T>(Up), dstate<T>(Ul), phys(h), s);
   HIPCHK(hipGetLastError());
