@@ -245,8 +245,14 @@ struct LevelIndex {
   // non-periodic domain.
   bool wrap(int (&c)[3]) const {
     for (int d = 0; d < h->ndim; ++d) {
-      if (h->p.bc[d] == AMR_BC_PERIODIC) c[d] = posmod(c[d], N[d]);
-      else if (c[d] < 0 || c[d] >= N[d]) return false;
+      if (h->p.bc[d] == AMR_BC_PERIODIC) {
+        // positions come within one period of the domain: no division then
+        if (c[d] < 0) c[d] += N[d];
+        else if (c[d] >= N[d]) c[d] -= N[d];
+        if (c[d] < 0 || c[d] >= N[d]) c[d] = posmod(c[d], N[d]);
+      } else if (c[d] < 0 || c[d] >= N[d]) {
+        return false;
+      }
     }
     return true;
   }
