@@ -81,12 +81,15 @@ def measured_traffic(workload, dtype, kernel="k_flux", launch_config=None):
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("source_sha256") != kernel_source_digest(kernel) or rec.get("dtype") != dtype:
-        return None
-    if launch_config is not None and rec.get("launch_config") != launch_config:
-        return None
-    return rec.get("traffic_bytes_per_launch")
+        data = json.load(fh)
+    # one record per profiled launch configuration
+    for rec in data.get("records", [data]):
+        if rec.get("source_sha256") != kernel_source_digest(kernel) or rec.get("dtype") != dtype:
+            continue
+        if launch_config is not None and rec.get("launch_config") != launch_config:
+            continue
+        return rec.get("traffic_bytes_per_launch")
+    return None
 
 
 def flux_kernel_flops(ndim, n, gv):

@@ -325,8 +325,10 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
 
 /* Launch configuration of the batched advance.  tile_policy 0: 16 x 16
  * thread tiles; 1: per grid and band, the tile width in [4, 64] (256 threads
- * per tile) that launches the fewest tiles over the grid.  zchunk: planes per
- * work item along z (3D).  launch_mode bit 0: persistent launches (a fixed
+ * per tile) that launches the fewest tiles over the grid.  zchunk: at most
+ * this many planes per work item of the flux or fused kernel along z (3D): a
+ * tile column of D planes is cut into ceil(D / zchunk) chunks of near-equal
+ * length.  launch_mode bit 0: persistent launches (a fixed
  * grid of resident blocks popping the launch's item list from a device
  * queue, one atomic per claim of items, in list order: finest level first,
  * then inside each eighth of the flux list its longest items (most

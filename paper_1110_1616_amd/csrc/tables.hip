@@ -85,7 +85,11 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   const int zlo = h->ndim == 3 ? cl : 0;
   const int ftw = pick_tile(ch[0] - cl, ch[1] - cl, 1, h->tile_policy), fth = 256 / ftw;
   check_tile(ftw);
-  for (int z0 = zlo; z0 < ch[2]; z0 += (h->ndim == 3 ? zc : 1))
+  // a column's planes in ceil(D / zc) chunks of near-equal length (each
+  // chunk recomputes a plane or two at its ends, so a short remainder chunk
+  // costs more per plane than an even split)
+  const int FD = ch[2] - zlo, fnz = h->ndim == 3 ? (FD + zc - 1) / zc : 1;
+  for (int zi = 0; zi < fnz; ++zi)
     for (int y0 = cl; y0 < ch[1]; y0 += fth - 1)
       for (int x0 = cl; x0 < ch[0]; x0 += ftw - 1) {
         FluxItem it{};
@@ -94,8 +98,8 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
         it.gv = gv;
         it.x0 = x0;
         it.y0 = y0;
-        it.z0 = z0;
-        it.z1 = h->ndim == 3 ? std::min(z0 + zc, ch[2]) : 1;
+        it.z0 = h->ndim == 3 ? zlo + (int)((int64_t)FD * zi / fnz) : 0;
+        it.z1 = h->ndim == 3 ? zlo + (int)((int64_t)FD * (zi + 1) / fnz) : 1;
         fl.push_back(it);
       }
   const int ul0 = -gv + 2;
@@ -123,8 +127,10 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
   if (!h->upwind_emf) {
     const int xtw = pick_tile(uh[0] - ul0, uh[1] - ul0, 2, h->tile_policy), xth = 256 / xtw;
     check_tile(xtw);
+    // the column's planes in near-equal chunks, as for the flux items
     const int xzhi = h->ndim == 3 ? uh[2] + 1 : 1;
-    for (int z0 = uzlo; z0 < xzhi; z0 += (h->ndim == 3 ? zc : 1))
+    const int D = xzhi - uzlo, nzc = h->ndim == 3 ? (D + zc - 1) / zc : 1;
+    for (int zi = 0; zi < nzc; ++zi)
       for (int y0 = ul0; y0 < uh[1]; y0 += xth - 2)
         for (int x0 = ul0; x0 < uh[0]; x0 += xtw - 2) {
           FluxItem it{};
@@ -133,8 +139,8 @@ void add_grid_items(amr_hierarchy* h, int gi, int gv, std::vector<FluxItem>& fl,
           it.gv = gv;
           it.x0 = x0;
           it.y0 = y0;
-          it.z0 = z0;
-          it.z1 = h->ndim == 3 ? std::min(z0 + zc, xzhi) : 1;
+          it.z0 = uzlo + (int)((int64_t)D * zi / nzc);
+          it.z1 = uzlo + (int)((int64_t)D * (zi + 1) / nzc);
           h->h_xitems.push_back(it);
         }
   }
