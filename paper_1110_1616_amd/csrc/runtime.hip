@@ -156,6 +156,16 @@ void do_dt(amr_hierarchy* h, const amr_state* Ua, const amr_state* Ub, uint32_t 
   HIPCHK(hipGetLastError());
 }
 
+// Whether level l > 0 needs its same-level band refresh before substeps
+// k >= 1.  A substep from band 4 also advances the band cells within 2 of
+// the interior, from the same inputs and with the same arithmetic as the
+// neighbours that own them (the decoupling by extended ghost zones), so
+// those cells already equal the neighbours' interiors bit for bit; only a
+// synchronisation with a finer level (restriction, reflux, EMF fix) can
+// change a level's interiors between its substeps.  The finest level has
+// none, and its refresh would copy equal values.
+static bool refresh_needed(const amr_hierarchy* h, int l) { return l + 1 < h->nlev; }
+
 // One coarse step of the whole hierarchy.  mode 0: batched launch cycles
 // (every level stepping in a cycle in one launch, finest level first); mode
 // 1: the serial level order with one launch per grid (the per-grid path).
@@ -176,9 +186,11 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
         const int span = ipow(R, L - 1 - l);
         if (c % span) continue;
         const int k = c / span;
-        // the refresh before substeps k >= 1 feeds a step from band 2
+        // the refresh before substeps k >= 1 feeds a step from band 2; on
+        // the finest level it is skipped (see refresh_needed)
         if (k % R == 0) do_fill<T>(h, l, AMR_FILL_FULL, cur(l), cur(l - 1), s);
-        else do_fill<T>(h, l, AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s, step_band(h, l, k) == 2);
+        else if (refresh_needed(h, l))
+          do_fill<T>(h, l, AMR_FILL_SAME_LEVEL, cur(l), cur(l - 1), s, step_band(h, l, k) == 2);
       }
       run_list<T>(h, lists[c], Ua, Ub, par, dt0, ws, s);
       // levels whose window ends here: every grid has stepped; registers
@@ -206,7 +218,8 @@ void coarse_step(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t& par, 
       par ^= 1u << l;
       if (l + 1 < L) {
         for (int kk = 0; kk < R; ++kk) {
-          if (kk > 0) do_fill<T>(h, l + 1, AMR_FILL_SAME_LEVEL, cur(l + 1), cur(l), s, step_band(h, l + 1, kk) == 2);
+          if (kk > 0 && refresh_needed(h, l + 1))
+            do_fill<T>(h, l + 1, AMR_FILL_SAME_LEVEL, cur(l + 1), cur(l), s, step_band(h, l + 1, kk) == 2);
           cyc(l + 1, kk);
         }
         do_sync<T>(h, l + 1, cur(l + 1), cur(l), ws, s);

@@ -97,6 +97,49 @@ def test_decoupling_invariant_bitwise(ndim, dtype):
     assert mism == 0
 
 
+@pytest.mark.parametrize("ndim,dtype", [(3, "f64"), (3, "f32"), (2, "f64")])
+def test_refresh_between_substeps_is_redundant_without_a_finer_level(ndim, dtype):
+    """After a grid's first substep from a band of 4, the band cells within
+    2 of its interior hold, bit for bit, the values its same-level
+    neighbours computed for their interiors (the decoupling invariant), so
+    re-copying them before the band-2 substep changes nothing.  The level
+    cycle therefore skips that refresh on the finest level, whose interiors
+    no synchronisation modifies between its substeps.  Checked here: the
+    band-2 substep after a same-level refill equals, bit for bit, the
+    band-2 substep without it, on every grid of a tiled periodic level."""
+    import torch
+    if ndim == 3:
+        N = (48, 40, 36)
+        xs, ys, zs = (0, 20, 48), (0, 18, 40), (0, 14, 36)
+        boxes = [((x0, y0, z0), (x1, y1, z1)) for x0, x1 in zip(xs, xs[1:]) for y0, y1 in zip(ys, ys[1:])
+                 for z0, z1 in zip(zs, zs[1:])]
+    else:
+        N = (64, 48)
+        xs, ys = (0, 22, 40, 64), (0, 26, 48)
+        boxes = [((x0, y0), (x1, y1)) for x0, x1 in zip(xs, xs[1:]) for y0, y1 in zip(ys, ys[1:])]
+    log(f"case: refresh redundancy {ndim}D {N} {dtype}, {len(boxes)} grids")
+    ic = I.smooth_mhd(ndim, N, seed=13, v_rms=0.15, b_rms=0.3, jump=True)
+    H = A.Hierarchy(ndim, N, [(0, lo, hi) for lo, hi in boxes], ghost=4, dtype=dtype, dx0=ic["dx"], gamma=GAMMA)
+    U, V = H.new_state(), H.new_state()
+    for gi, (prim, b) in enumerate(_split_fields(ic, boxes)):
+        H.load_primitive(U, gi, prim, b)
+    H.fill(0, A.AMR_FILL_SAME_LEVEL, U)
+    H.dt0.fill_(1.0e-3)
+    H.advance(U, V, cycle=0, band=4)
+    Vr = H.new_state()
+    Vr.copy_(V)
+    H.fill(0, A.AMR_FILL_SAME_LEVEL, Vr)   # the refresh
+    Wr, W = H.new_state(), H.new_state()
+    H.advance(Vr, Wr, cycle=0, band=2)
+    H.advance(V, W, cycle=0, band=2)
+    torch.cuda.synchronize()
+    assert H.error_flags()[0] == 0
+    for gi in range(len(boxes)):
+        a, b = H.store_interior(Wr, gi), H.store_interior(W, gi)
+        for s in range(8):
+            assert np.array_equal(a[s], b[s]), (gi, A.FIELDS[s])
+
+
 def test_band_too_narrow_is_refused():
     log("case: refusals of bands too narrow for the substeps")
     N0 = (16, 16, 16)
