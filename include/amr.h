@@ -349,8 +349,9 @@ amr_status amr_load_primitive_adjoint(amr_hierarchy* h, int32_t grid, const doub
  * size never changes results.  Every configuration gives bitwise identical
  * results (the device code contracts multiply-adds only inside a source
  * expression, so an expression rounds the same way in every kernel).
- * Changing tile_policy or zchunk rebuilds the work lists and drops captured
- * graphs.  Default: 1, 16, 0. */
+ * Changing tile_policy, zchunk or the XCD chunking (bit 1: items are ordered
+ * longest first inside each XCD's chunk, else over the whole list) rebuilds
+ * the work lists and drops captured graphs.  Default: 1, 16, 0. */
 amr_status amr_set_launch_config(amr_hierarchy* h, int32_t tile_policy, int32_t zchunk, int32_t launch_mode);
 amr_status amr_get_launch_config(const amr_hierarchy* h, int32_t* tile_policy, int32_t* zchunk, int32_t* launch_mode);
 

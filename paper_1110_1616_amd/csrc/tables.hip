@@ -175,22 +175,22 @@ LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& g
   L.fused.n = (int)h->h_xitems.size() - L.fused.off;
   L.flux.n = (int)h->h_fitems.size() - L.flux.off;
   L.upd.n = (int)h->h_uitems.size() - L.upd.off;
-  // longest flux items first inside each eighth of the list (the XCD chunks
-  // of the launch): blocks take items in list order, so the short ones
-  // (a grid's last z-chunk) fill the end of the launch instead of starting
-  // late; items stay in their chunk, next to the tiles they share halos with
-  const int C = (L.flux.n + 7) / 8;
-  for (int c = 0; c < 8 && c * C < L.flux.n; ++c) {
-    auto b = h->h_fitems.begin() + L.flux.off + c * C;
-    auto e = h->h_fitems.begin() + L.flux.off + std::min(L.flux.n, (c + 1) * C);
-    std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
-  }
-  const int CX = (L.fused.n + 7) / 8;
-  for (int c = 0; c < 8 && c * CX < L.fused.n; ++c) {
-    auto b = h->h_xitems.begin() + L.fused.off + c * CX;
-    auto e = h->h_xitems.begin() + L.fused.off + std::min(L.fused.n, (c + 1) * CX);
-    std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
-  }
+  // longest items first (most z-planes): blocks take items in list order,
+  // so the short ones fill the end of the launch instead of starting late.
+  // With XCD chunking the order holds inside each eighth of the list (the
+  // chunks of the launch), so items stay in their chunk, next to the tiles
+  // they share halos with; without it, over the whole list.
+  auto longest_first = [&](std::vector<FluxItem>& v, int off, int n) {
+    const int parts = h->xcd_chunks ? 8 : 1;
+    const int C = (n + parts - 1) / parts;
+    for (int c = 0; c < parts && c * C < n; ++c) {
+      auto b = v.begin() + off + c * C;
+      auto e = v.begin() + off + std::min(n, (c + 1) * C);
+      std::stable_sort(b, e, [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
+    }
+  };
+  longest_first(h->h_fitems, L.flux.off, L.flux.n);
+  longest_first(h->h_xitems, L.fused.off, L.fused.n);
   return L;
 }
 
@@ -1062,11 +1062,13 @@ void set_launch_config(amr_hierarchy* h, int policy, int zchunk, int mode) {
   h->persistent = (mode & 1) != 0;
   h->claim = 1 << ((mode >> 4) & 3);
   h->persistent_flux = (mode & 5) != 0;
-  h->xcd_chunks = (mode & 2) != 0;
+  const bool xcd = (mode & 2) != 0;
   h->fused = (mode & 8) != 0;
-  if (policy != h->tile_policy || zchunk != h->zchunk) {
+  // the item order depends on the XCD chunking (see make_list)
+  if (policy != h->tile_policy || zchunk != h->zchunk || xcd != h->xcd_chunks) {
     h->tile_policy = policy;
     h->zchunk = zchunk;
+    h->xcd_chunks = xcd;
     rebuild_lists(h);
   }
 }
