@@ -10,7 +10,9 @@
 // (from the state carried from plane k-1), and the fluxes go to LDS, double
 // buffered over two planes.  From them come the edge EMFs E_z of plane k and
 // E_x, E_y at z = k - 1/2, and the update of plane k-1 (cells and their x-
-// and y-faces) and of the z-faces at k - 1/2.  A tile updates the cells of
+// and y-faces) and of the z-faces at k - 1/2.  A plane takes two barriers in
+// 3-D: the update reads E_z of the plane below (from the iteration before)
+// and forms the neighbours' E_x, E_y again from their inputs in LDS.  A tile updates the cells of
 // lanes tx in [1, tw-2], ty in [1, th-2] (their high faces and the edges
 // around them are computed in the tile); tiles overlap by two columns and
 // rows (the last x- and y-face of the update region go to the lane that
@@ -56,7 +58,8 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
   __shared__ T sH[2][10][256];  // hydro components 0..4 of the x- (0..4) and y-face (5..9) fluxes, by plane parity
   __shared__ T sB[4][256];      // EMF inputs of this plane: F_x c5, F_y c6, F_z c5, F_z c6 (2-D: F_x c6, F_y c5)
   __shared__ T sEz[2][256];     // E_z at each lane's (x, y) low corner, by plane parity
-  __shared__ T sExy[2][256];    // E_x, E_y at each lane's low z-edges of the current level
+  __shared__ T sX6[2][256];     // 3-D: F_x c6 and F_y c5 of each lane, by plane parity (the inputs of
+  __shared__ T sY5[2][256];     // the neighbours' E_x, E_y, formed again where the z-faces need them)
   __shared__ int s_claim[2], s_c;
   if (threadIdx.x == 0) s_c = 0;
 
@@ -265,6 +268,8 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
       if (NDIM == 3) {
         sB[2][tid] = fz[5];
         sB[3][tid] = fz[6];
+        sX6[pb][tid] = fx[6];
+        sY5[pb][tid] = fy[5];
       } else {
         sB[2][tid] = fx[6];
         sB[3][tid] = fy[5];
@@ -277,10 +282,11 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
       if (NDIM == 3 && k >= z0) {
         if (yf) ex = emf_mean(fy5p, fy[5], sB[3][tid - tw], fz[6]);
         if (xf) ey = emf_mean(sB[2][tid - 1], fz[5], fx6p, fx[6]);
-        sExy[0][tid] = ex;
-        sExy[1][tid] = ey;
       }
-      __syncthreads();
+      // 2-D: the faces read E_z of the neighbours' corners, formed above; in
+      // 3-D every input of this plane's update is in LDS already (E_z of the
+      // plane below, and the inputs of the neighbours' E_x, E_y)
+      if (NDIM == 2) __syncthreads();
       if (NDIM == 3) {
         // the old values of everything this plane updates are loaded before
         // any store, so their latencies overlap
@@ -299,7 +305,11 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
         if (cup && uby) uo[6] = ldb(U.f[6], ec);
         // z-faces at k - 1/2 (element of plane k)
         if (zup) {
-          const T ey1 = sExy[1][tid + 1], ex1 = sExy[0][tid + tw];
+          // E_y of the next lane's and E_x of the next row's low z-edge,
+          // from the same inputs as those lanes form them
+          const int qb = kk & 1;
+          const T ey1 = emf_mean(sB[2][tid], sB[2][tid + 1], sX6[qb][tid + 1], sX6[pb][tid + 1]);
+          const T ex1 = emf_mean(sY5[qb][tid + tw], sY5[pb][tid + tw], sB[3][tid], sB[3][tid + tw]);
           stb(V.f[7], eb, uo[7] - curl_delta(cdx, ey1, ey, cdy, ex1, ex));
         }
         // cells and x-, y-faces of plane k - 1
