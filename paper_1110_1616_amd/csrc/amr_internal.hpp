@@ -64,6 +64,10 @@ template <class T> struct DevState {
 // element of the face's high-side cell (face index f along d <-> cell f).
 template <class T> struct DevFlux {
   T* f[3][7];
+  // the same 21 arrays as one base and the byte stride from one to the next
+  // (f[d][q] = base + (7 d + q) stride)
+  char* base;
+  uint64_t stride;
   // upwinded EMF only (else null): cell-centred reference EMF per component,
   // and the edge EMFs computed from it once per edge
   T* e[3];

@@ -38,6 +38,27 @@ namespace amr {
 
 namespace {
 
+// Both state sets, indexed by level parity per work item (a kernel-argument
+// block read where an item starts, not held in registers across items).
+template <class T> struct StatePair {
+  DevState<T> s[2];
+};
+// A masked store of a face's seven flux components forms the arrays'
+// addresses from the base and stride where it stores (the empty asm keeps
+// the 21 addresses from being formed once and held in scalar registers
+// through the plane loop, which spilled them).
+template <class T, class B>
+__device__ __forceinline__ void st_flux7(const DevFlux<T>& F, int d, B b, const T (&v)[7]) {
+  uint64_t p = reinterpret_cast<uint64_t>(F.base), st = F.stride;
+  asm volatile("" : "+s"(p), "+s"(st));
+  p += (uint64_t)(7 * d) * st;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    *reinterpret_cast<__attribute__((address_space(1))) T*>(p + b) = v[c];
+    p += st;
+  }
+}
+
 // Lane t of a tile dimension tdim is the one that stores (for the
 // registers) coordinate c of a computed range [clo, chi]: tiles overlap by
 // two, so interior lanes [1, tdim-2] own their coordinate and the edge lanes
@@ -48,7 +69,7 @@ __device__ __forceinline__ bool owns(int t, int tdim, int c, int clo, int chi) {
 
 template <class T, int NDIM, bool PERSIST>
 __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grids, const FluxItem* __restrict__ items,
-                                               int nitems, DevState<T> S0, DevState<T> S1, uint32_t parity,
+                                               int nitems, StatePair<T> S, uint32_t parity,
                                                DevFlux<T> F, const uint8_t* __restrict__ fmask,
                                                const double* __restrict__ dt0p, Phys ph, ErrBlock* err, WorkQueue* q,
                                                bool xcd, int claim) {
@@ -74,8 +95,8 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
     const FluxItem item = items[it];
     const GridDesc G = grids[item.grid];
     const bool odd = (parity >> G.level) & 1u;
-    const DevState<T> U = odd ? S1 : S0;
-    const DevState<T> V = odd ? S0 : S1;
+    const DevState<T> U = S.s[odd ? 1 : 0];
+    const DevState<T> V = S.s[odd ? 0 : 1];
     const Idx<NDIM> ix(G);
     const IdxB<NDIM, T> bx(G);
     const int gv = item.gv;
@@ -236,8 +257,7 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
         for (int c = 0; c < 7; ++c) l[c] = sX[c][tid - 1];
         hlld7(l, pr.m[0], bn[0], gam, fx);
         if ((mk & 1u) && sxy_x && sxy_y && (NDIM == 2 || (k >= z0 && k < z1) || (k == kstart && z0 == ul)))
-#pragma unroll
-          for (int c = 0; c < 7; ++c) stb(F.f[0][c], eb, fx[c]);
+          st_flux7(F, 0, eb, fx);
       }
       if (yf) {
         T l[7];
@@ -245,14 +265,12 @@ __global__ __launch_bounds__(256) void k_fused(const GridDesc* __restrict__ grid
         for (int c = 0; c < 7; ++c) l[c] = sY[c][tid - tw];
         hlld7(l, pr.m[1], bn[1], gam, fy);
         if ((mk & 2u) && sxy_x && sxy_y && (NDIM == 2 || (k >= z0 && k < z1) || (k == kstart && z0 == ul)))
-#pragma unroll
-          for (int c = 0; c < 7; ++c) stb(F.f[1][c], eb, fy[c]);
+          st_flux7(F, 1, eb, fy);
       }
       if (zf) {
         hlld7(zcarry, pr.m[2], bn[2], gam, fz);
         if ((mk & 4u) && sxy_x && sxy_y && k < z1)
-#pragma unroll
-          for (int c = 0; c < 7; ++c) stb(F.f[2][c], eb, fz[c]);
+          st_flux7(F, 2, eb, fz);
       }
       if (NDIM == 3) {
 #pragma unroll
@@ -377,9 +395,12 @@ void launch_fused(int ndim, const GridDesc* grids, const FluxItem* items, int ni
   if (nitems <= 0) return;
   const bool per = pblocks > 0 && q != nullptr;
   const dim3 grid(per ? std::min(pblocks, nitems) : claim_blocks(nitems, claim, xcd)), block(256);
+  StatePair<T> SP;
+  SP.s[0] = S0;
+  SP.s[1] = S1;
 #define AMR_FUSED_LAUNCH(ND, P) \
-  hipLaunchKernelGGL((k_fused<T, ND, P>), grid, block, 0, s, grids, items, nitems, S0, S1, parity, F, fmask, dt0, ph, err, q, xcd, \
-                     claim)
+  hipLaunchKernelGGL((k_fused<T, ND, P>), grid, block, 0, s, grids, items, nitems, SP, parity, F, fmask, dt0, ph, err, q, \
+                     xcd, claim)
   if (ndim == 3) {
     if (per) AMR_FUSED_LAUNCH(3, true);
     else AMR_FUSED_LAUNCH(3, false);

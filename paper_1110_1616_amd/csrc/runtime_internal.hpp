@@ -347,6 +347,8 @@ template <class T> DevFlux<T> dflux(const amr_hierarchy* h, void* ws) {
   DevFlux<T> F;
   char* base = (char*)ws;
   const int64_t stride = h->total_elems * (int64_t)sizeof(T);
+  F.base = base;
+  F.stride = (uint64_t)stride;
   for (int d = 0; d < 3; ++d)
     for (int q = 0; q < 7; ++q) F.f[d][q] = (T*)(base + (int64_t)(d * 7 + q) * stride);
   for (int a = 0; a < 3; ++a) {
