@@ -632,103 +632,122 @@ void build_sync_tables(amr_hierarchy* h, int f) {
   FI.build(h, f);
   for (int a = 0; a < nd; ++a)
     if (CI.N[a] >= (1 << 20)) throw Error(AMR_EUNSUPPORTED, "level exceeds 2^20 cells along an axis");
-  // covered(p) for coarse cells p of the current coarse grid's box grown by
-  // one cell: a mask filled from the fine grids' boxes (and their periodic
-  // images) before the grid's elements are visited
-  std::vector<uint8_t> mask, near;  // near: a covered cell within one cell (any direction)
-  int mlo[3] = {0, 0, 0}, mext[3] = {1, 1, 1};
-  auto near_covered = [&](const int (&pc)[3]) {
-    int64_t o = 0;
-    for (int a = 2; a >= 0; --a) o = o * mext[a] + (pc[a] - mlo[a]);
-    return near[o] != 0;
-  };
-  auto covered = [&](const int (&pc)[3]) {
-    int64_t o = 0;
-    for (int a = 2; a >= 0; --a) {
-      const int x = pc[a] - mlo[a];
-      if (x < 0 || x >= mext[a]) throw Error(AMR_EINVAL, "internal: covered() outside the grid's mask");
-      o = o * mext[a] + x;
-    }
-    return mask[o] != 0;
-  };
-  auto build_mask = [&](const amr_grid& CG) {
-    for (int a = 0; a < 3; ++a) {
-      mlo[a] = a < nd ? CG.lo[a] - 1 : 0;
-      mext[a] = a < nd ? CG.hi[a] - CG.lo[a] + 2 : 1;
-    }
-    mask.assign((size_t)mext[0] * mext[1] * mext[2], 0);
-    for (int fgi : h->level_grids[f]) {
-      const amr_grid& FG = h->grids[fgi];
-      // coarse box of the fine grid (boxes are aligned to R), then every
-      // periodic image that meets the mask box
-      int flo[3], fhi[3];
-      for (int a = 0; a < 3; ++a) {
-        flo[a] = a < nd ? FG.lo[a] / R : 0;
-        fhi[a] = a < nd ? FG.hi[a] / R : 1;
-      }
-      for (int sz = -1; sz <= 1; ++sz)
-        for (int sy = -1; sy <= 1; ++sy)
-          for (int sx = -1; sx <= 1; ++sx) {
-            const int sh[3] = {sx, sy, sz};
-            int lo[3], hi[3];
-            bool ok = true;
-            for (int a = 0; a < 3; ++a) {
-              if (a >= nd || h->p.bc[a] != AMR_BC_PERIODIC) {
-                if (sh[a] != 0) ok = false;
-                lo[a] = std::max(flo[a], mlo[a]);
-                hi[a] = std::min(fhi[a], mlo[a] + mext[a]);
-              } else {
-                const int off = sh[a] * CI.N[a];
-                lo[a] = std::max(flo[a] + off, mlo[a]);
-                hi[a] = std::min(fhi[a] + off, mlo[a] + mext[a]);
-              }
-              ok = ok && lo[a] < hi[a];
-            }
-            if (!ok) continue;
-            for (int z = lo[2]; z < hi[2]; ++z)
-              for (int y = lo[1]; y < hi[1]; ++y)
-                for (int x = lo[0]; x < hi[0]; ++x)
-                  mask[((size_t)(z - mlo[2]) * mext[1] + (y - mlo[1])) * mext[0] + (x - mlo[0])] = 1;
-          }
-    }
-    near.assign(mask.size(), 0);
-    for (int z = 0; z < mext[2]; ++z)
-      for (int y = 0; y < mext[1]; ++y)
-        for (int x = 0; x < mext[0]; ++x) {
-          if (!mask[((size_t)z * mext[1] + y) * mext[0] + x]) continue;
-          for (int dz = (nd == 3 ? -1 : 0); dz <= (nd == 3 ? 1 : 0); ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-              for (int dx = -1; dx <= 1; ++dx) {
-                const int X = x + dx, Y = y + dy, Z = z + dz;
-                if (X < 0 || Y < 0 || Z < 0 || X >= mext[0] || Y >= mext[1] || Z >= mext[2]) continue;
-                near[((size_t)Z * mext[1] + Y) * mext[0] + X] = 1;
-              }
-        }
-  };
-  // fine grid owning fine cell p (unwrapped); shift = wrap(p) - p
-  LevelIndex::Memo fmemo;
-  auto fine_owner = [&](const int (&p)[3], int (&shift)[3]) {
-    int w[3] = {p[0], p[1], p[2]};
-    if (!FI.wrap(w)) return -1;
-    for (int a = 0; a < 3; ++a) shift[a] = w[a] - p[a];
-    return FI.find_cell(w, fmemo);
-  };
   const double dxc[3] = {h->p.dx0[0] / ipow(R, c), h->p.dx0[1] / ipow(R, c), nd == 3 ? h->p.dx0[2] / ipow(R, c) : 1.0};
   SyncTables& T = h->sync[f];
-  std::vector<FaceRegEntry> frc, frf;
-  std::vector<EdgeRegEntry> erc, erf;
-  std::vector<RefluxEntry> rfx;
-  std::vector<EmfFixEntry> efx;
-  std::vector<RestrictEntry> rst;
   // edge registers deduplicated by (axis, wrapped edge index): the key packs
   // the axis and three coordinates below 2^20 each
-  std::unordered_map<int64_t, int> edge_id;
   auto edge_key = [](int a, const int (&w)[3]) {
     return (((int64_t)a << 60) | ((int64_t)w[2] << 40) | ((int64_t)w[1] << 20) | (int64_t)w[0]);
   };
-  int nfreg = 0;
-
-  for (int gi : h->level_grids[c]) {
+  // Coarse grids are independent: worker threads build each grid's entries
+  // with grid-local register numbers (edge registers deduplicated within the
+  // grid); a pass in grid order then numbers the face registers one after
+  // another and each edge register where it first appears, which gives the
+  // tables of a single pass over the grids in order.
+  struct LocalEdge {
+    int64_t key;
+    EdgeRegEntry c, f;
+  };
+  struct GridSync {
+    std::vector<FaceRegEntry> frc, frf;
+    std::vector<RefluxEntry> rfx;
+    std::vector<EmfFixEntry> efx;  // reg[]: indices into edges
+    std::vector<RestrictEntry> rst;
+    std::vector<LocalEdge> edges;
+    int nfreg = 0;
+  };
+  const std::vector<int>& cgrids = h->level_grids[c];
+  std::vector<GridSync> per(cgrids.size());
+  parallel_for(cgrids.size(), [&](size_t slot) {
+    const int gi = cgrids[slot];
+    GridSync& out = per[slot];
+    std::vector<FaceRegEntry>&frc = out.frc, &frf = out.frf;
+    std::vector<RefluxEntry>& rfx = out.rfx;
+    std::vector<EmfFixEntry>& efx = out.efx;
+    std::vector<RestrictEntry>& rst = out.rst;
+    int& nfreg = out.nfreg;
+    std::unordered_map<int64_t, int> edge_id;  // key -> index in out.edges
+    // covered(p) for coarse cells p of the current coarse grid's box grown by
+    // one cell: a mask filled from the fine grids' boxes (and their periodic
+    // images) before the grid's elements are visited
+    std::vector<uint8_t> mask, near;  // near: a covered cell within one cell (any direction)
+    int mlo[3] = {0, 0, 0}, mext[3] = {1, 1, 1};
+    auto near_covered = [&](const int (&pc)[3]) {
+      int64_t o = 0;
+      for (int a = 2; a >= 0; --a) o = o * mext[a] + (pc[a] - mlo[a]);
+      return near[o] != 0;
+    };
+    auto covered = [&](const int (&pc)[3]) {
+      int64_t o = 0;
+      for (int a = 2; a >= 0; --a) {
+        const int x = pc[a] - mlo[a];
+        if (x < 0 || x >= mext[a]) throw Error(AMR_EINVAL, "internal: covered() outside the grid's mask");
+        o = o * mext[a] + x;
+      }
+      return mask[o] != 0;
+    };
+    auto build_mask = [&](const amr_grid& CG) {
+      for (int a = 0; a < 3; ++a) {
+        mlo[a] = a < nd ? CG.lo[a] - 1 : 0;
+        mext[a] = a < nd ? CG.hi[a] - CG.lo[a] + 2 : 1;
+      }
+      mask.assign((size_t)mext[0] * mext[1] * mext[2], 0);
+      for (int fgi : h->level_grids[f]) {
+        const amr_grid& FG = h->grids[fgi];
+        // coarse box of the fine grid (boxes are aligned to R), then every
+        // periodic image that meets the mask box
+        int flo[3], fhi[3];
+        for (int a = 0; a < 3; ++a) {
+          flo[a] = a < nd ? FG.lo[a] / R : 0;
+          fhi[a] = a < nd ? FG.hi[a] / R : 1;
+        }
+        for (int sz = -1; sz <= 1; ++sz)
+          for (int sy = -1; sy <= 1; ++sy)
+            for (int sx = -1; sx <= 1; ++sx) {
+              const int sh[3] = {sx, sy, sz};
+              int lo[3], hi[3];
+              bool ok = true;
+              for (int a = 0; a < 3; ++a) {
+                if (a >= nd || h->p.bc[a] != AMR_BC_PERIODIC) {
+                  if (sh[a] != 0) ok = false;
+                  lo[a] = std::max(flo[a], mlo[a]);
+                  hi[a] = std::min(fhi[a], mlo[a] + mext[a]);
+                } else {
+                  const int off = sh[a] * CI.N[a];
+                  lo[a] = std::max(flo[a] + off, mlo[a]);
+                  hi[a] = std::min(fhi[a] + off, mlo[a] + mext[a]);
+                }
+                ok = ok && lo[a] < hi[a];
+              }
+              if (!ok) continue;
+              for (int z = lo[2]; z < hi[2]; ++z)
+                for (int y = lo[1]; y < hi[1]; ++y)
+                  for (int x = lo[0]; x < hi[0]; ++x)
+                    mask[((size_t)(z - mlo[2]) * mext[1] + (y - mlo[1])) * mext[0] + (x - mlo[0])] = 1;
+            }
+      }
+      near.assign(mask.size(), 0);
+      for (int z = 0; z < mext[2]; ++z)
+        for (int y = 0; y < mext[1]; ++y)
+          for (int x = 0; x < mext[0]; ++x) {
+            if (!mask[((size_t)z * mext[1] + y) * mext[0] + x]) continue;
+            for (int dz = (nd == 3 ? -1 : 0); dz <= (nd == 3 ? 1 : 0); ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  const int X = x + dx, Y = y + dy, Z = z + dz;
+                  if (X < 0 || Y < 0 || Z < 0 || X >= mext[0] || Y >= mext[1] || Z >= mext[2]) continue;
+                  near[((size_t)Z * mext[1] + Y) * mext[0] + X] = 1;
+                }
+          }
+    };
+    // fine grid owning fine cell p (unwrapped); shift = wrap(p) - p
+    LevelIndex::Memo fmemo;
+    auto fine_owner = [&](const int (&p)[3], int (&shift)[3]) {
+      int w[3] = {p[0], p[1], p[2]};
+      if (!FI.wrap(w)) return -1;
+      for (int a = 0; a < 3; ++a) shift[a] = w[a] - p[a];
+      return FI.find_cell(w, fmemo);
+    };
     const GridDesc& C = h->desc[gi];
     const amr_grid& CG = h->grids[gi];
     build_mask(CG);
@@ -876,7 +895,7 @@ void build_sync_tables(amr_hierarchy* h, int f) {
                 int re;
                 auto it = edge_id.find(key);
                 if (it == edge_id.end()) {
-                  re = (int)edge_id.size();
+                  re = (int)out.edges.size();
                   edge_id[key] = re;
                   EdgeRegEntry ec{};
                   ec.reg = re;
@@ -884,7 +903,6 @@ void build_sync_tables(amr_hierarchy* h, int f) {
                   ec.grid = gi;
                   ec.n = 1;
                   ec.e[0] = (int32_t)elem(C, nd, e[0] - CG.lo[0], e[1] - CG.lo[1], e[2] - CG.lo[2]);
-                  erc.push_back(ec);
                   const amr_grid& FG = h->grids[fg];
                   EdgeRegEntry ef{};
                   ef.reg = re;
@@ -897,7 +915,7 @@ void build_sync_tables(amr_hierarchy* h, int f) {
                     if (ea < nd) p[ea] += s2;
                     ef.e[ef.n++] = (int32_t)elem(h->desc[fg], nd, p[0], p[1], p[2]);
                   }
-                  erf.push_back(ef);
+                  out.edges.push_back(LocalEdge{key, ec, ef});
                 } else {
                   re = it->second;
                 }
@@ -910,6 +928,53 @@ void build_sync_tables(amr_hierarchy* h, int f) {
             if (fx.n > 0) efx.push_back(fx);
           }
     }
+  });
+  // grid order: face registers numbered consecutively, edge registers at
+  // their first appearance
+  std::vector<FaceRegEntry> frc, frf;
+  std::vector<EdgeRegEntry> erc, erf;
+  std::vector<RefluxEntry> rfx;
+  std::vector<EmfFixEntry> efx;
+  std::vector<RestrictEntry> rst;
+  std::unordered_map<int64_t, int> edge_id;
+  int nfreg = 0;
+  std::vector<int> gid;
+  for (GridSync& g : per) {
+    for (FaceRegEntry e : g.frc) {
+      e.reg += nfreg;
+      frc.push_back(e);
+    }
+    for (FaceRegEntry e : g.frf) {
+      e.reg += nfreg;
+      frf.push_back(e);
+    }
+    for (RefluxEntry e : g.rfx) {
+      for (int i = 0; i < e.n; ++i) e.reg[i] += nfreg;
+      rfx.push_back(e);
+    }
+    nfreg += g.nfreg;
+    gid.resize(g.edges.size());
+    for (size_t k = 0; k < g.edges.size(); ++k) {
+      LocalEdge& le = g.edges[k];
+      auto it = edge_id.find(le.key);
+      if (it != edge_id.end()) {
+        gid[k] = it->second;
+        continue;
+      }
+      const int id = (int)edge_id.size();
+      edge_id[le.key] = id;
+      gid[k] = id;
+      le.c.reg = id;
+      le.f.reg = id;
+      erc.push_back(le.c);
+      erf.push_back(le.f);
+    }
+    for (EmfFixEntry e : g.efx) {
+      for (int i = 0; i < e.n; ++i) e.reg[i] = gid[e.reg[i]];
+      efx.push_back(e);
+    }
+    rst.insert(rst.end(), g.rst.begin(), g.rst.end());
+    g = GridSync();
   }
   T.nfreg = nfreg;
   T.nereg = (int)edge_id.size();
