@@ -380,7 +380,10 @@ typedef struct {
  * z-chunk, claims of 2, 4 and 8 items per block (launch mode bits 4-5,
  * entries 104..106), each over `reps` passes of every launch cycle's batched
  * advance, reading each level's current buffer (parity) and writing the
- * other one, and keeps the fastest of all 107.  The state the
+ * other one, and keeps the fastest of all 107.  Only the advance launches
+ * are timed; before each cycle's launch the band fills that open level
+ * windows there run as in a coarse step (they rewrite the values the bands
+ * already hold), so the advance meets the caches as in a coarse step.  The state the
  * next amr_coarse_step() reads is not changed.  results: host array of
  * AMR_TUNE_CANDIDATES entries or NULL; *chosen (or NULL): index of the kept
  * entry.  Synchronises the stream; drops captured graphs. */
