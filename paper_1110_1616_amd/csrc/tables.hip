@@ -190,7 +190,43 @@ LaunchList make_list(amr_hierarchy* h, const std::vector<std::pair<int, int>>& g
     }
   };
   longest_first(h->h_fitems, L.flux.off, L.flux.n);
-  longest_first(h->h_xitems, L.fused.off, L.fused.n);
+  // The last fused items of the list (the shortest, about the last 8% of
+  // the work, counting each item's planes plus the three a chunk adds) are
+  // cut into chunks of at most 8 planes: when the queue runs dry each block
+  // is left with a short item, so the launch's tail shrinks.  Each piece
+  // recomputes its chunk's end planes, as any z-chunk does, so results do
+  // not change.  Only lists without XCD chunks: there every eighth of the
+  // list drains on its own.
+  if (!h->xcd_chunks && h->ndim == 3 && L.fused.n > 0) {
+    std::vector<FluxItem> v(h->h_xitems.begin() + L.fused.off, h->h_xitems.end());
+    std::stable_sort(v.begin(), v.end(), [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
+    int64_t total = 0;
+    for (const FluxItem& it : v) total += it.z1 - it.z0 + 3;
+    std::vector<FluxItem> out;
+    out.reserve(v.size() + v.size() / 4);
+    int64_t acc = 0;
+    for (const FluxItem& it : v) {
+      const int D = it.z1 - it.z0;
+      acc += D + 3;
+      if (acc * 100 > total * 92 && D > 8) {
+        const int n = (D + 7) / 8;
+        for (int i = 0; i < n; ++i) {
+          FluxItem piece = it;
+          piece.z0 = it.z0 + D * i / n;
+          piece.z1 = it.z0 + D * (i + 1) / n;
+          out.push_back(piece);
+        }
+      } else {
+        out.push_back(it);
+      }
+    }
+    std::stable_sort(out.begin(), out.end(), [](const FluxItem& x, const FluxItem& y) { return x.z1 - x.z0 > y.z1 - y.z0; });
+    h->h_xitems.resize(L.fused.off);
+    h->h_xitems.insert(h->h_xitems.end(), out.begin(), out.end());
+    L.fused.n = (int)out.size();
+  } else {
+    longest_first(h->h_xitems, L.fused.off, L.fused.n);
+  }
   return L;
 }
 
