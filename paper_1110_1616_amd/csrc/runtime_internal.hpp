@@ -221,25 +221,42 @@ inline int ipow(int b, int e) {
 inline int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 inline int posmod(int a, int b) { return ((a % b) + b) % b; }
 
-// Spatial lookup of grids of one level by 16-cell buckets.
+// Spatial lookup of the grids of one level by cubic buckets of cells.
 struct LevelIndex {
   const amr_hierarchy* h = nullptr;
   int level = 0;
   int N[3] = {1, 1, 1};
-  std::unordered_map<int64_t, std::vector<int>> buckets;
-  static constexpr int B = 16;
-  int64_t key(int bx, int by, int bz) const { return ((int64_t)bz * 1000003 + by) * 1000003 + bx; }
+  // the level's domain cut into cubic buckets of B cells (16, doubled until
+  // there are at most 2^21 buckets); each bucket lists the grids meeting it,
+  // in grid order (bgrid[bstart[b] .. bstart[b + 1]))
+  int B = 16;
+  int NB[3] = {1, 1, 1};
+  std::vector<int> bstart, bgrid;
   void build(const amr_hierarchy* hh, int l) {
     h = hh;
     level = l;
     for (int d = 0; d < 3; ++d) N[d] = d < h->ndim ? h->p.domain[d] * ipow(h->R, l) : 1;
-    for (int gi : h->level_grids[l]) {
-      const amr_grid& G = h->grids[gi];
-      for (int bz = floordiv(G.lo[2], B); bz <= floordiv(G.hi[2] - 1, B); ++bz)
-        for (int by = floordiv(G.lo[1], B); by <= floordiv(G.hi[1] - 1, B); ++by)
-          for (int bx = floordiv(G.lo[0], B); bx <= floordiv(G.hi[0] - 1, B); ++bx)
-            buckets[key(bx, by, bz)].push_back(gi);
-    }
+    auto nb = [&](int d) { return d < h->ndim ? (N[d] + B - 1) / B : 1; };
+    B = 16;
+    while ((int64_t)nb(0) * nb(1) * nb(2) > ((int64_t)1 << 21)) B *= 2;
+    for (int d = 0; d < 3; ++d) NB[d] = nb(d);
+    const int64_t nbk = (int64_t)NB[0] * NB[1] * NB[2];
+    bstart.assign(nbk + 1, 0);
+    auto each_bucket = [&](const amr_grid& G, auto&& fn) {
+      int lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = d < h->ndim ? G.lo[d] / B : 0;
+        hi[d] = d < h->ndim ? (G.hi[d] - 1) / B : 0;
+      }
+      for (int bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+          for (int bx = lo[0]; bx <= hi[0]; ++bx) fn(((int64_t)bz * NB[1] + by) * NB[0] + bx);
+    };
+    for (int gi : h->level_grids[l]) each_bucket(h->grids[gi], [&](int64_t b) { ++bstart[b + 1]; });
+    for (int64_t b = 0; b < nbk; ++b) bstart[b + 1] += bstart[b];
+    bgrid.assign(bstart[nbk], -1);
+    std::vector<int> fill(bstart.begin(), bstart.end() - 1);
+    for (int gi : h->level_grids[l]) each_bucket(h->grids[gi], [&](int64_t b) { bgrid[fill[b]++] = gi; });
   }
   // Wrap a cell position on periodic axes; returns false if outside a
   // non-periodic domain.
@@ -275,9 +292,11 @@ struct LevelIndex {
   int find_cell(const int (&c)[3], Memo& memo) const {
     for (int m = 0; m < 8; ++m)
       if (holds(memo.g[m], c)) return memo.g[m];
-    auto it = buckets.find(key(floordiv(c[0], B), floordiv(c[1], B), floordiv(c[2], B)));
-    if (it == buckets.end()) return -1;
-    for (int gi : it->second) {
+    for (int d = 0; d < 3; ++d)
+      if (c[d] < 0 || c[d] >= N[d]) return -1;
+    const int64_t b = ((int64_t)(c[2] / B) * NB[1] + c[1] / B) * NB[0] + c[0] / B;
+    for (int i = bstart[b]; i < bstart[b + 1]; ++i) {
+      const int gi = bgrid[i];
       if (holds(gi, c)) {
         memo.g[memo.turn++ & 7] = gi;
         return gi;
