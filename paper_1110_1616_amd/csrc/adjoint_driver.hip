@@ -65,7 +65,7 @@ void build_adjoint_tables(amr_hierarchy* h, int level) {
     t.e1 = std::max<int64_t>(t.e1, G.off + box);
   }
   // transpose of the same-level band copy: group (class, source) -> dsts
-  const std::vector<CopyEntry>& cp = h->h_copy[level];
+  const RawVec<CopyEntry>& cp = h->h_copy[level];
   const int4 cb = h->copy_cls[level];
   const int bounds[4] = {cb.x, cb.y, cb.z, cb.w};
   std::vector<std::pair<int64_t, int32_t>> keyed;  // (class * 2^32 + src, dst)

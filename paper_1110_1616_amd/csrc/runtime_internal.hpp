@@ -49,7 +49,21 @@ struct Error : std::runtime_error {
 
 #define HIPCHK_NOTHROW(x) (void)(x)
 
-template <class T> T* dev_upload(const std::vector<T>& v) {
+// Allocator whose value-less construct leaves trivially constructible
+// elements uninitialised: large host tables sized first and then filled by
+// worker threads are not zeroed (and paged in) by one thread beforehand.
+template <class T> struct DefaultInitAlloc : std::allocator<T> {
+  template <class U> struct rebind {
+    using other = DefaultInitAlloc<U>;
+  };
+  DefaultInitAlloc() = default;
+  template <class U> DefaultInitAlloc(const DefaultInitAlloc<U>&) {}
+  template <class U> void construct(U* p) { ::new ((void*)p) U; }
+  template <class U, class... A> void construct(U* p, A&&... a) { ::new ((void*)p) U(std::forward<A>(a)...); }
+};
+template <class T> using RawVec = std::vector<T, DefaultInitAlloc<T>>;
+
+template <class T, class A> T* dev_upload(const std::vector<T, A>& v) {
   if (v.empty() || g_host_only) return nullptr;
   T* p = nullptr;
   HIPCHK(hipMalloc((void**)&p, v.size() * sizeof(T)));
@@ -112,7 +126,7 @@ struct amr_hierarchy {
 
   // fill maps per level (host copies of the same-level copy maps are kept
   // for the adjoint's transpose)
-  std::vector<std::vector<CopyEntry>> h_copy;
+  std::vector<amrrt::RawVec<CopyEntry>> h_copy;
   std::vector<CopyEntry*> d_copy;
   std::vector<int> n_copy;
   std::vector<int4> copy_cls;
@@ -272,6 +286,18 @@ struct LevelIndex {
       }
     }
     return true;
+  }
+  // One axis of wrap(): the wrapped position, or -1 outside a non-periodic
+  // domain.
+  int wrap1(int a, int v) const {
+    if (a >= h->ndim) return v;
+    if (h->p.bc[a] == AMR_BC_PERIODIC) {
+      if (v < 0) v += N[a];
+      else if (v >= N[a]) v -= N[a];
+      if (v < 0 || v >= N[a]) v = posmod(v, N[a]);
+      return v;
+    }
+    return (v < 0 || v >= N[a]) ? -1 : v;
   }
   bool holds(int gi, const int (&c)[3]) const {
     if (gi < 0 || gi >= (int)h->grids.size()) return false;

@@ -432,7 +432,8 @@ void build_fill_maps(amr_hierarchy* h) {
     std::vector<GridMaps> per(lg.size());
     auto one_grid = [&](size_t slot) {
     const int gi = lg[slot];
-    LevelIndex::Memo same, par;  // lookups of this grid's band on its level and the parent's
+    LevelIndex::Memo par;  // lookups of this grid's band on the parent level
+    std::vector<int> qa[3], qb[3], occ[3], sel[3], owna, ownb;
     std::vector<CopyEntry>(&cp)[4] = per[slot].cp;
     std::vector<CopyEntry>(&cp2)[4] = per[slot].cp2;
     std::vector<ProlongEntry>& pc = per[slot].pc;
@@ -443,65 +444,82 @@ void build_fill_maps(amr_hierarchy* h) {
       for (int cls = 0; cls < ncls; ++cls) {
         int lo[3], hi[3];
         class_extent(G, nd, cls, lo, hi);
+        const int fa = cls - 1;  // normal axis of a face class, -1 for cells
+        int ext[3];
+        for (int a = 0; a < 3; ++a) ext[a] = hi[a] - lo[a];
+        // Per axis and band index x: the wrapped position of the cell holding
+        // the element (qa; positions clamped into the domain first on outflow
+        // axes) and, along a face class's normal, of the cell below it (qb);
+        // -1 where that cell lies outside an outflow domain.
+        for (int a = 0; a < 3; ++a) {
+          qa[a].resize(ext[a]);
+          qb[a].resize(ext[a]);
+          for (int x = 0; x < ext[a]; ++x) {
+            int v = GG.lo[a] + lo[a] + x;
+            if (a < nd && h->p.bc[a] != AMR_BC_PERIODIC) {
+              const int top = (cls == 1 + a) ? LI.N[a] : LI.N[a] - 1;
+              v = std::min(std::max(v, 0), top);
+            }
+            qa[a][x] = LI.wrap1(a, v);
+            qb[a][x] = a == fa ? LI.wrap1(a, v - 1) : qa[a][x];
+          }
+        }
+        // owner[x]: the grid of this level holding cell qa (ownb: cell qb),
+        // painted from each grid that holds any of them (the grids of a level
+        // are disjoint, so no element is painted twice)
+        const size_t nel = (size_t)ext[0] * ext[1] * ext[2];
+        owna.assign(nel, -1);
+        if (fa >= 0) ownb.assign(nel, -1);
+        auto paint = [&](std::vector<int>(&q)[3], std::vector<int>& own) {
+          for (int a = 0; a < 3; ++a) {
+            occ[a].assign(LI.N[a] + 1, 0);
+            for (int v : q[a])
+              if (v >= 0) occ[a][v + 1] = 1;
+            for (int v = 0; v < LI.N[a]; ++v) occ[a][v + 1] += occ[a][v];
+          }
+          for (int sg : lg) {
+            const amr_grid& S = h->grids[sg];
+            bool hit = true;
+            for (int a = 0; a < 3 && hit; ++a) hit = occ[a][S.hi[a]] - occ[a][S.lo[a]] > 0;
+            if (!hit) continue;
+            for (int a = 0; a < 3; ++a) {
+              sel[a].clear();
+              for (int x = 0; x < ext[a]; ++x)
+                if (q[a][x] >= S.lo[a] && q[a][x] < S.hi[a]) sel[a].push_back(x);
+            }
+            for (int z : sel[2])
+              for (int y : sel[1])
+                for (int x : sel[0]) own[((size_t)z * ext[1] + y) * ext[0] + x] = sg;
+          }
+        };
+        paint(qa, owna);
+        if (fa >= 0) paint(qb, ownb);
         for (int k = lo[2]; k < hi[2]; ++k)
           for (int j = lo[1]; j < hi[1]; ++j)
             for (int i = lo[0]; i < hi[0]; ++i) {
               const int x[3] = {i, j, k};
               if (own_elem(G, nd, cls, x)) continue;
-              // global position, then (for level 0 outflow) clamp into the domain
-              int p[3] = {GG.lo[0] + i, GG.lo[1] + j, GG.lo[2] + k};
-              bool outside = false;
-              for (int a = 0; a < nd; ++a) {
-                if (h->p.bc[a] == AMR_BC_PERIODIC) continue;
-                const int top = (cls == 1 + a) ? LI.N[a] : LI.N[a] - 1;
-                if (p[a] < 0) { p[a] = 0; outside = true; }
-                if (p[a] > top) { p[a] = top; outside = true; }
-              }
-              (void)outside;
-              // find a same-level source: the element must be a cell of, or a
-              // face on the boundary of, another grid's interior (lowest id)
+              const int xi[3] = {i - lo[0], j - lo[1], k - lo[2]};
+              const size_t o = ((size_t)xi[2] * ext[1] + xi[1]) * ext[0] + xi[0];
+              // a same-level source: the lowest-id grid of this level whose
+              // interior holds the element as a cell, or as a face on its
+              // boundary (the cell above or below the face along its normal)
               int src_grid = -1;
               int sp[3] = {0, 0, 0};
-              // candidates: the cell itself and, for faces, the cell below
-              // along the normal (faces on a grid's high boundary)
-              for (int cand = 0; cand < 2 && src_grid < 0; ++cand) {
-                if (cand == 1 && cls == 0) break;
-                int c[3] = {p[0], p[1], p[2]};
-                if (cand == 1) c[cls - 1] -= 1;
-                int w[3] = {c[0], c[1], c[2]};
-                if (!LI.wrap(w)) continue;
-                int s = LI.find_cell(w, same);
-                if (s < 0) continue;
-                // the element itself, in the wrapped frame of grid s
-                int e[3] = {w[0], w[1], w[2]};
-                if (cand == 1) e[cls - 1] += 1;
-                // prefer the lowest grid id among grids sharing a face
-                if (cand == 0 && cls > 0) {
-                  int c2[3] = {w[0], w[1], w[2]};
-                  c2[cls - 1] -= 1;
-                  int w2[3] = {c2[0], c2[1], c2[2]};
-                  if (LI.wrap(w2)) {
-                    int s2 = LI.find_cell(w2, same);
-                    if (s2 >= 0 && s2 < s) {
-                      s = s2;
-                      e[0] = w2[0];
-                      e[1] = w2[1];
-                      e[2] = w2[2];
-                      e[cls - 1] += 1;
-                    }
-                  }
-                }
-                if (s == gi) {
-                  // own grid through a periodic image: allowed only if the
-                  // element differs from this band position
-                  bool same = e[0] == GG.lo[0] + i && e[1] == GG.lo[1] + j && e[2] == GG.lo[2] + k;
-                  if (same) continue;
-                }
-                src_grid = s;
-                sp[0] = e[0];
-                sp[1] = e[1];
-                sp[2] = e[2];
-              }
+              const int band_pos[3] = {GG.lo[0] + i, GG.lo[1] + j, GG.lo[2] + k};
+              auto take = [&](int sg, std::vector<int>(&q)[3], int up) {
+                int e[3] = {q[0][xi[0]], q[1][xi[1]], q[2][xi[2]]};
+                if (up >= 0) e[up] += 1;
+                // the own grid through a periodic image only at another position
+                if (sg == gi && e[0] == band_pos[0] && e[1] == band_pos[1] && e[2] == band_pos[2]) return false;
+                src_grid = sg;
+                for (int a = 0; a < 3; ++a) sp[a] = e[a];
+                return true;
+              };
+              bool found = false;
+              const int sa = owna[o], sb = fa >= 0 ? ownb[o] : -1;
+              if (sa >= 0) found = (sb >= 0 && sb < sa) ? take(sb, qb, fa) : take(sa, qa, -1);
+              if (!found && sb >= 0) found = take(sb, qb, fa);
               const int64_t dst = elem(G, nd, i, j, k);
               if (src_grid >= 0) {
                 const GridDesc& S = h->desc[src_grid];
@@ -592,8 +610,8 @@ void build_fill_maps(amr_hierarchy* h) {
       opc[g + 1] = opc[g] + per[g].pc.size();
       opf[g + 1] = opf[g] + per[g].pf.size();
     }
-    std::vector<CopyEntry> all(o1[4 * ng]), all2(o2[4 * ng]);
-    std::vector<ProlongEntry> pc(opc[ng]), pf(opf[ng]);
+    RawVec<CopyEntry> all(o1[4 * ng]), all2(o2[4 * ng]);
+    RawVec<ProlongEntry> pc(opc[ng]), pf(opf[ng]);
     parallel_for(ng, [&](size_t g) {
       GridMaps& m = per[g];
       for (int c = 0; c < 4; ++c) {
