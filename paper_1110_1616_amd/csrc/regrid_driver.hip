@@ -272,10 +272,10 @@ std::vector<amr_grid> do_regrid(amr_hierarchy* h, int level, amr_state* Ul, amr_
 
 // (O)verlap maps of one level of hn from the previous iteration ho.
 struct OverlapMaps {
-  std::vector<CopyEntry> cp;  // cells, then x-, y-, z-faces
+  RawVec<CopyEntry> cp;  // cells, then x-, y-, z-faces
   int4 cls = make_int4(0, 0, 0, 0);
-  std::vector<ProlongEntry> pc, pf;
-  std::vector<ProjEntry> pj;
+  RawVec<ProlongEntry> pc, pf;
+  RawVec<ProjEntry> pj;
 };
 
 OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int l) {
@@ -299,24 +299,45 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
     const GridDesc& G = hn->desc[gi];
     int n[3] = {1, 1, 1};
     for (int a = 0; a < nd; ++a) n[a] = GG.hi[a] - GG.lo[a];
-    // old owner of the element; for faces the lower old grid id of the two
-    // cells that share it
-    auto old_src = [&](int cls, const int (&p)[3], int64_t& src) -> bool {
-      int best = -1;
-      int be[3] = {0, 0, 0};
-      for (int cand = 0; cand < (cls == 0 ? 1 : 2); ++cand) {
-        int w[3] = {p[0], p[1], p[2]};
-        if (cand == 1) w[cls - 1] -= 1;
-        if (!OI.wrap(w)) continue;
-        const int og = OI.find_cell(w, omemo);
-        if (og < 0) continue;
-        if (best < 0 || og < best) {
-          best = og;
-          be[0] = w[0];
-          be[1] = w[1];
-          be[2] = w[2];
-          if (cand == 1) be[cls - 1] += 1;
+    // old owner of the element: the old grid of this level holding the cell
+    // (qa), or for faces the lower old grid id of the two cells that share it
+    // (qb: the cell below along the normal), from owner maps painted per
+    // class from the old grids that hold any of those cells
+    std::vector<int> qa[3], qb[3], occ[3], sel[3], owna, ownb;
+    int top[3] = {1, 1, 1};
+    auto paint = [&](std::vector<int>(&q)[3], std::vector<int>& own) {
+      own.assign((size_t)top[0] * top[1] * top[2], -1);
+      for (int a = 0; a < 3; ++a) {
+        occ[a].assign(OI.N[a] + 1, 0);
+        for (int v : q[a])
+          if (v >= 0) occ[a][v + 1] = 1;
+        for (int v = 0; v < OI.N[a]; ++v) occ[a][v + 1] += occ[a][v];
+      }
+      for (int og : ho->level_grids[l]) {
+        const amr_grid& S = ho->grids[og];
+        bool hit = true;
+        for (int a = 0; a < 3 && hit; ++a) hit = occ[a][S.hi[a]] - occ[a][S.lo[a]] > 0;
+        if (!hit) continue;
+        for (int a = 0; a < 3; ++a) {
+          sel[a].clear();
+          for (int x = 0; x < top[a]; ++x)
+            if (q[a][x] >= S.lo[a] && q[a][x] < S.hi[a]) sel[a].push_back(x);
         }
+        for (int z : sel[2])
+          for (int y : sel[1])
+            for (int x : sel[0]) own[((size_t)z * top[1] + y) * top[0] + x] = og;
+      }
+    };
+    auto old_src = [&](int cls, int i, int j, int k, int64_t& src) -> bool {
+      const size_t o = ((size_t)k * top[1] + j) * top[0] + i;
+      const int sa = owna[o], sb = cls > 0 ? ownb[o] : -1;
+      int best = sa, be[3];
+      const int xi[3] = {i, j, k};
+      for (int a = 0; a < 3; ++a) be[a] = qa[a][xi[a]];
+      if (sb >= 0 && (best < 0 || sb < best)) {
+        best = sb;
+        for (int a = 0; a < 3; ++a) be[a] = qb[a][xi[a]];
+        be[cls - 1] += 1;
       }
       if (best < 0) return false;
       const amr_grid& SG = ho->grids[best];
@@ -325,15 +346,24 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
     };
     for (int cls = 0; cls < (nd == 3 ? 4 : 3); ++cls) {
       const int d = cls - 1;
-      int top[3];
-      for (int a = 0; a < 3; ++a) top[a] = a < nd ? n[a] + ((cls > 0 && a == d) ? 1 : 0) : 1;
+      for (int a = 0; a < 3; ++a) {
+        top[a] = a < nd ? n[a] + ((cls > 0 && a == d) ? 1 : 0) : 1;
+        qa[a].resize(top[a]);
+        qb[a].resize(top[a]);
+        for (int x = 0; x < top[a]; ++x) {
+          qa[a][x] = OI.wrap1(a, GG.lo[a] + x);
+          qb[a][x] = a == d ? OI.wrap1(a, GG.lo[a] + x - 1) : qa[a][x];
+        }
+      }
+      paint(qa, owna);
+      if (cls > 0) paint(qb, ownb);
       for (int k = 0; k < top[2]; ++k)
         for (int j = 0; j < top[1]; ++j)
           for (int i = 0; i < top[0]; ++i) {
             const int p[3] = {GG.lo[0] + i, GG.lo[1] + j, GG.lo[2] + k};
             const int64_t dst = elem(G, nd, i, j, k);
             int64_t src = 0;
-            if (old_src(cls, p, src)) {
+            if (old_src(cls, i, j, k, src)) {
               m.cp[cls].push_back(CopyEntry{(int32_t)dst, (int32_t)src});
               continue;
             }
@@ -404,20 +434,32 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
         }
   };
   parallel_for(lg.size(), one);
+  // concatenation: copies class by class, each in grid order; the rest in
+  // grid order; every grid's lists go to offsets known in advance, copied
+  // by the worker threads
+  const size_t ng = per.size();
+  std::vector<size_t> oc(4 * ng + 1, 0), opc(ng + 1, 0), opf(ng + 1, 0), opj(ng + 1, 0);
+  for (int c = 0; c < 4; ++c)
+    for (size_t g = 0; g < ng; ++g) oc[c * ng + g + 1] = oc[c * ng + g] + per[g].cp[c].size();
+  for (size_t g = 0; g < ng; ++g) {
+    opc[g + 1] = opc[g] + per[g].pc.size();
+    opf[g + 1] = opf[g] + per[g].pf.size();
+    opj[g + 1] = opj[g] + per[g].pj.size();
+  }
   OverlapMaps M;
-  for (int c = 0; c < 4; ++c) {
-    for (Per& m : per) M.cp.insert(M.cp.end(), m.cp[c].begin(), m.cp[c].end());
-    const int v = (int)M.cp.size();
-    if (c == 0) M.cls.x = v;
-    if (c == 1) M.cls.y = v;
-    if (c == 2) M.cls.z = v;
-    if (c == 3) M.cls.w = v;
-  }
-  for (Per& m : per) {
-    M.pc.insert(M.pc.end(), m.pc.begin(), m.pc.end());
-    M.pf.insert(M.pf.end(), m.pf.begin(), m.pf.end());
-    M.pj.insert(M.pj.end(), m.pj.begin(), m.pj.end());
-  }
+  M.cp.resize(oc[4 * ng]);
+  M.pc.resize(opc[ng]);
+  M.pf.resize(opf[ng]);
+  M.pj.resize(opj[ng]);
+  M.cls = make_int4((int)oc[ng], (int)oc[2 * ng], (int)oc[3 * ng], (int)oc[4 * ng]);
+  parallel_for(ng, [&](size_t g) {
+    Per& m = per[g];
+    for (int c = 0; c < 4; ++c) std::copy(m.cp[c].begin(), m.cp[c].end(), M.cp.begin() + oc[c * ng + g]);
+    std::copy(m.pc.begin(), m.pc.end(), M.pc.begin() + opc[g]);
+    std::copy(m.pf.begin(), m.pf.end(), M.pf.begin() + opf[g]);
+    std::copy(m.pj.begin(), m.pj.end(), M.pj.begin() + opj[g]);
+    m = Per();
+  });
   return M;
 }
 
