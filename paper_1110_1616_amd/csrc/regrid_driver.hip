@@ -303,31 +303,9 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
     // (qa), or for faces the lower old grid id of the two cells that share it
     // (qb: the cell below along the normal), from owner maps painted per
     // class from the old grids that hold any of those cells
-    std::vector<int> qa[3], qb[3], occ[3], sel[3], owna, ownb;
+    std::vector<int> qa[3], qb[3], owna, ownb;
+    PaintScratch ps;
     int top[3] = {1, 1, 1};
-    auto paint = [&](std::vector<int>(&q)[3], std::vector<int>& own) {
-      own.assign((size_t)top[0] * top[1] * top[2], -1);
-      for (int a = 0; a < 3; ++a) {
-        occ[a].assign(OI.N[a] + 1, 0);
-        for (int v : q[a])
-          if (v >= 0) occ[a][v + 1] = 1;
-        for (int v = 0; v < OI.N[a]; ++v) occ[a][v + 1] += occ[a][v];
-      }
-      for (int og : ho->level_grids[l]) {
-        const amr_grid& S = ho->grids[og];
-        bool hit = true;
-        for (int a = 0; a < 3 && hit; ++a) hit = occ[a][S.hi[a]] - occ[a][S.lo[a]] > 0;
-        if (!hit) continue;
-        for (int a = 0; a < 3; ++a) {
-          sel[a].clear();
-          for (int x = 0; x < top[a]; ++x)
-            if (q[a][x] >= S.lo[a] && q[a][x] < S.hi[a]) sel[a].push_back(x);
-        }
-        for (int z : sel[2])
-          for (int y : sel[1])
-            for (int x : sel[0]) own[((size_t)z * top[1] + y) * top[0] + x] = og;
-      }
-    };
     auto old_src = [&](int cls, int i, int j, int k, int64_t& src) -> bool {
       const size_t o = ((size_t)k * top[1] + j) * top[0] + i;
       const int sa = owna[o], sb = cls > 0 ? ownb[o] : -1;
@@ -355,8 +333,8 @@ OverlapMaps build_overlap(const amr_hierarchy* hn, const amr_hierarchy* ho, int 
           qb[a][x] = a == d ? OI.wrap1(a, GG.lo[a] + x - 1) : qa[a][x];
         }
       }
-      paint(qa, owna);
-      if (cls > 0) paint(qb, ownb);
+      paint_owners(ho, ho->level_grids[l], qa, owna, ps);
+      if (cls > 0) paint_owners(ho, ho->level_grids[l], qb, ownb, ps);
       for (int k = 0; k < top[2]; ++k)
         for (int j = 0; j < top[1]; ++j)
           for (int i = 0; i < top[0]; ++i) {

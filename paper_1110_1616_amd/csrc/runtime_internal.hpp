@@ -240,37 +240,21 @@ struct LevelIndex {
   const amr_hierarchy* h = nullptr;
   int level = 0;
   int N[3] = {1, 1, 1};
-  // the level's domain cut into cubic buckets of B cells (16, doubled until
-  // there are at most 2^21 buckets); each bucket lists the grids meeting it,
-  // in grid order (bgrid[bstart[b] .. bstart[b + 1]))
-  int B = 16;
-  int NB[3] = {1, 1, 1};
-  std::vector<int> bstart, bgrid;
+  // buckets of B^3 cells (sparse: fine levels cover little of their domain)
+  std::unordered_map<int64_t, std::vector<int>> buckets;
+  static constexpr int B = 16;
+  int64_t key(int bx, int by, int bz) const { return ((int64_t)bz * 1000003 + by) * 1000003 + bx; }
   void build(const amr_hierarchy* hh, int l) {
     h = hh;
     level = l;
     for (int d = 0; d < 3; ++d) N[d] = d < h->ndim ? h->p.domain[d] * ipow(h->R, l) : 1;
-    auto nb = [&](int d) { return d < h->ndim ? (N[d] + B - 1) / B : 1; };
-    B = 16;
-    while ((int64_t)nb(0) * nb(1) * nb(2) > ((int64_t)1 << 21)) B *= 2;
-    for (int d = 0; d < 3; ++d) NB[d] = nb(d);
-    const int64_t nbk = (int64_t)NB[0] * NB[1] * NB[2];
-    bstart.assign(nbk + 1, 0);
-    auto each_bucket = [&](const amr_grid& G, auto&& fn) {
-      int lo[3], hi[3];
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = d < h->ndim ? G.lo[d] / B : 0;
-        hi[d] = d < h->ndim ? (G.hi[d] - 1) / B : 0;
-      }
-      for (int bz = lo[2]; bz <= hi[2]; ++bz)
-        for (int by = lo[1]; by <= hi[1]; ++by)
-          for (int bx = lo[0]; bx <= hi[0]; ++bx) fn(((int64_t)bz * NB[1] + by) * NB[0] + bx);
-    };
-    for (int gi : h->level_grids[l]) each_bucket(h->grids[gi], [&](int64_t b) { ++bstart[b + 1]; });
-    for (int64_t b = 0; b < nbk; ++b) bstart[b + 1] += bstart[b];
-    bgrid.assign(bstart[nbk], -1);
-    std::vector<int> fill(bstart.begin(), bstart.end() - 1);
-    for (int gi : h->level_grids[l]) each_bucket(h->grids[gi], [&](int64_t b) { bgrid[fill[b]++] = gi; });
+    for (int gi : h->level_grids[l]) {
+      const amr_grid& G = h->grids[gi];
+      for (int bz = floordiv(G.lo[2], B); bz <= floordiv(G.hi[2] - 1, B); ++bz)
+        for (int by = floordiv(G.lo[1], B); by <= floordiv(G.hi[1] - 1, B); ++by)
+          for (int bx = floordiv(G.lo[0], B); bx <= floordiv(G.hi[0] - 1, B); ++bx)
+            buckets[key(bx, by, bz)].push_back(gi);
+    }
   }
   // Wrap a cell position on periodic axes; returns false if outside a
   // non-periodic domain.
@@ -318,11 +302,9 @@ struct LevelIndex {
   int find_cell(const int (&c)[3], Memo& memo) const {
     for (int m = 0; m < 8; ++m)
       if (holds(memo.g[m], c)) return memo.g[m];
-    for (int d = 0; d < 3; ++d)
-      if (c[d] < 0 || c[d] >= N[d]) return -1;
-    const int64_t b = ((int64_t)(c[2] / B) * NB[1] + c[1] / B) * NB[0] + c[0] / B;
-    for (int i = bstart[b]; i < bstart[b + 1]; ++i) {
-      const int gi = bgrid[i];
+    auto it = buckets.find(key(floordiv(c[0], B), floordiv(c[1], B), floordiv(c[2], B)));
+    if (it == buckets.end()) return -1;
+    for (int gi : it->second) {
       if (holds(gi, c)) {
         memo.g[memo.turn++ & 7] = gi;
         return gi;
@@ -335,6 +317,54 @@ struct LevelIndex {
     return find_cell(c, m);
   }
 };
+
+// Owner map of a box of positions: own[(z * ny + y) * nx + x] is the grid
+// among `grids` (disjoint boxes) whose interior holds the cell
+// (q[0][x], q[1][y], q[2][z]), or -1; a negative q (a position outside the
+// domain) has no owner.  A grid is tested against the runs of consecutive
+// positions on each axis and painted where it holds them, so the cost goes
+// with the grids near the box, not with the box's elements times the grids.
+struct PaintScratch {
+  std::vector<std::pair<int, int>> runs[3];
+  std::vector<int> vals, sel[3];
+};
+inline void paint_owners(const amr_hierarchy* h, const std::vector<int>& grids, const std::vector<int> (&q)[3],
+                         std::vector<int>& own, PaintScratch& ps) {
+  const size_t nx = q[0].size(), ny = q[1].size(), nz = q[2].size();
+  own.assign(nx * ny * nz, -1);
+  for (int a = 0; a < 3; ++a) {
+    ps.vals.clear();
+    for (int v : q[a])
+      if (v >= 0) ps.vals.push_back(v);
+    std::sort(ps.vals.begin(), ps.vals.end());
+    ps.runs[a].clear();
+    for (int v : ps.vals) {
+      if (!ps.runs[a].empty() && v <= ps.runs[a].back().second) {
+        ps.runs[a].back().second = std::max(ps.runs[a].back().second, v + 1);
+        continue;
+      }
+      ps.runs[a].push_back({v, v + 1});
+    }
+  }
+  for (int g : grids) {
+    const amr_grid& S = h->grids[g];
+    bool hit = true;
+    for (int a = 0; a < 3 && hit; ++a) {
+      bool any = false;
+      for (const auto& r : ps.runs[a]) any = any || (r.first < S.hi[a] && S.lo[a] < r.second);
+      hit = any;
+    }
+    if (!hit) continue;
+    for (int a = 0; a < 3; ++a) {
+      ps.sel[a].clear();
+      for (int x = 0; x < (int)q[a].size(); ++x)
+        if (q[a][x] >= S.lo[a] && q[a][x] < S.hi[a]) ps.sel[a].push_back(x);
+    }
+    for (int z : ps.sel[2])
+      for (int y : ps.sel[1])
+        for (int x : ps.sel[0]) own[((size_t)z * ny + y) * nx + x] = g;
+  }
+}
 
 // Pool element of (i, j, k) in grid G; every table entry goes through here,
 // so an index outside the grid's padded box is caught on the host.

@@ -433,7 +433,8 @@ void build_fill_maps(amr_hierarchy* h) {
     auto one_grid = [&](size_t slot) {
     const int gi = lg[slot];
     LevelIndex::Memo par;  // lookups of this grid's band on the parent level
-    std::vector<int> qa[3], qb[3], occ[3], sel[3], owna, ownb;
+    std::vector<int> qa[3], qb[3], owna, ownb;
+    PaintScratch ps;
     std::vector<CopyEntry>(&cp)[4] = per[slot].cp;
     std::vector<CopyEntry>(&cp2)[4] = per[slot].cp2;
     std::vector<ProlongEntry>& pc = per[slot].pc;
@@ -464,36 +465,9 @@ void build_fill_maps(amr_hierarchy* h) {
             qb[a][x] = a == fa ? LI.wrap1(a, v - 1) : qa[a][x];
           }
         }
-        // owner[x]: the grid of this level holding cell qa (ownb: cell qb),
-        // painted from each grid that holds any of them (the grids of a level
-        // are disjoint, so no element is painted twice)
-        const size_t nel = (size_t)ext[0] * ext[1] * ext[2];
-        owna.assign(nel, -1);
-        if (fa >= 0) ownb.assign(nel, -1);
-        auto paint = [&](std::vector<int>(&q)[3], std::vector<int>& own) {
-          for (int a = 0; a < 3; ++a) {
-            occ[a].assign(LI.N[a] + 1, 0);
-            for (int v : q[a])
-              if (v >= 0) occ[a][v + 1] = 1;
-            for (int v = 0; v < LI.N[a]; ++v) occ[a][v + 1] += occ[a][v];
-          }
-          for (int sg : lg) {
-            const amr_grid& S = h->grids[sg];
-            bool hit = true;
-            for (int a = 0; a < 3 && hit; ++a) hit = occ[a][S.hi[a]] - occ[a][S.lo[a]] > 0;
-            if (!hit) continue;
-            for (int a = 0; a < 3; ++a) {
-              sel[a].clear();
-              for (int x = 0; x < ext[a]; ++x)
-                if (q[a][x] >= S.lo[a] && q[a][x] < S.hi[a]) sel[a].push_back(x);
-            }
-            for (int z : sel[2])
-              for (int y : sel[1])
-                for (int x : sel[0]) own[((size_t)z * ext[1] + y) * ext[0] + x] = sg;
-          }
-        };
-        paint(qa, owna);
-        if (fa >= 0) paint(qb, ownb);
+        // owner maps: the grid of this level holding cell qa (ownb: cell qb)
+        paint_owners(h, lg, qa, owna, ps);
+        if (fa >= 0) paint_owners(h, lg, qb, ownb, ps);
         for (int k = lo[2]; k < hi[2]; ++k)
           for (int j = lo[1]; j < hi[1]; ++j)
             for (int i = lo[0]; i < hi[0]; ++i) {
