@@ -137,8 +137,9 @@ def test_graph_replay_matches_eager_every_replay():
 @pytest.mark.parametrize("key", ["3d", "2d"])
 def test_every_launch_configuration_gives_identical_results(key):
     """Tile policy, z-chunk, persistent vs one-block-per-item launches (both
-    kernels or the flux kernel only), XCD chunking, the update's z-chunk,
-    the claim size and the fused flux-update kernel (launch mode bit 3) only
+    kernels or the flux kernel only), XCD chunking (fused lists without it
+    end in re-cut short items), the update's z-chunk, the claim size and
+    the fused flux-update kernel (launch mode bit 3) only
     change how the same per-face and per-cell arithmetic is distributed, and
     the device code contracts multiply-adds inside each source expression
     only: two coarse steps agree bit for bit under all 64 configurations
