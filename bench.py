@@ -251,8 +251,11 @@ def amr_workload(args, deep=False):
             st["par"] = H.graph_launch(st["par"])
 
     def tune():
+        # five passes per candidate (three on the deep hierarchy, whose pass
+        # is 32 launch cycles long): the leading candidates differ by well
+        # under 1%
         with torch.cuda.stream(stream):
-            return H.autotune(Ua, Ub, st["par"], reps=3)
+            return H.autotune(Ua, Ub, st["par"], reps=3 if deep else 5)
 
     desc = (f"{L}-level AMR hierarchy, R=2, 3D ideal MHD {args.dtype}: base {N0[0]}^3, {len(grids)} grids of even "
             f"extents {'8..48 (log-uniform)' if deep else '8..32'} (levels {cells} cells), each level covering 12.5% "
