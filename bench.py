@@ -180,7 +180,7 @@ def single_grid_workload(args):
                 "sample": f"oracle, same {N}^3 input, first {steps} steps (band 4 refilled every 2 steps)"}
 
     def tune():
-        return H.autotune(state["U"], state["V"], 0, reps=3)
+        return H.autotune(state["U"], state["V"], 0, reps=5)
 
     return (H, step, (lambda k: flops_per_step_pair * k / 2.0), (lambda k: upd_per_step_pair * k / 2.0), info,
             cpu_sample, tune)
