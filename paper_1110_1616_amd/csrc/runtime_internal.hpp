@@ -321,9 +321,10 @@ struct LevelIndex {
 // Owner map of a box of positions: own[(z * ny + y) * nx + x] is the grid
 // among `grids` (disjoint boxes) whose interior holds the cell
 // (q[0][x], q[1][y], q[2][z]), or -1; a negative q (a position outside the
-// domain) has no owner.  A grid is tested against the runs of consecutive
-// positions on each axis and painted where it holds them, so the cost goes
-// with the grids near the box, not with the box's elements times the grids.
+// domain) has no owner.  Each grid is tested against the runs of consecutive
+// positions on each axis (a few comparisons) and painted only where it holds
+// them, so the cost is the number of grids plus the painted elements, not
+// their product.
 struct PaintScratch {
   std::vector<std::pair<int, int>> runs[3];
   std::vector<int> vals, sel[3];
