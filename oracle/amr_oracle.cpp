@@ -475,7 +475,7 @@ struct Amr {
                 for (int up = 0; up < 2; ++up) {
                   int e[3] = {pf[0], pf[1], pf[2]};
                   e[da] += up;
-                  int fg, ew[3];
+                  int fg = -1, ew[3] = {0, 0, 0};
                   if (!cf_edge(c, ea, e, fg, ew)) continue;
                   int le[3] = {e[0] - q.lo[0], e[1] - q.lo[1], e[2] - q.lo[2]};
                   double dE = fine_emf_sum(f, ea, ew, fg) - dtc * q.coarse_cap.E(ea, le[0], le[1], le[2]);
