@@ -1,9 +1,11 @@
 """Parity at the benchmark's full sizes, in the launch configuration it
 times: the 3-level FP64 hierarchy (base 112^3, 549 grids, 4.3M cells) for
-one coarse step replayed from a captured HIP graph under the tuned launch
-configuration and the predictive schedule, and the 128^3 single grid (FP64
-and FP32) for a band-4 step pair, each against the FP64 oracle on every
-element."""
+one coarse step replayed from a captured HIP graph in the configuration the
+autotuner picks there (fused advance, persistent launches, z-chunk 32,
+window-start schedule), checked against the FP64 oracle on every element
+and bit for bit against the two-kernel path under the predictive schedule;
+and the 128^3 single grid (FP64 and FP32) for a band-4 step pair in its
+tuned configuration (fused, XCD chunks), against the oracle."""
 
 import numpy as np
 import pytest
@@ -24,15 +26,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_amr3_full_size_graph_replay_matches_oracle():
+def _amr3_graph_step(grids, fields, N0, L, cfg, schedule):
     import torch
-    N0, L = (112, 112, 112), 3
-    grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
-    fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
-    log(f"case: 3-level hierarchy base 112^3, {len(grids)} grids, launch config 1,12,6,2, eta schedule, graph replay")
     H = A.Hierarchy(3, N0, grids, nlevels=L, ghost=4)
-    H.set_launch_config(1, 12, 6, 2)
-    H.set_schedule(1)
+    H.set_launch_config(*cfg)
+    H.set_schedule(schedule)
     Ua, Ub = H.new_state(), H.new_state()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -45,13 +43,27 @@ def test_amr3_full_size_graph_replay_matches_oracle():
     torch.cuda.synchronize()
     assert H.error_flags()[0] == 0
     got = [H.store_interior(H.current(Ua, Ub, par, l), gi) for gi, (l, lo, hi) in enumerate(grids)]
+    return got, float(H.dt0.item())
+
+
+def test_amr3_full_size_graph_replay_matches_oracle():
+    N0, L = (112, 112, 112), 3
+    grids = I.amr_hierarchy(3, N0, L, seed=3, ext=(8, 32))
+    fields = I.amr_fields(3, N0, L, grids, seed=3, b_rms=0.3)
+    log(f"case: 3-level hierarchy base 112^3, {len(grids)} grids, launch config 1,32,12,2, schedule 0, graph replay")
+    got, dt0 = _amr3_graph_step(grids, fields, N0, L, (1, 32, 12, 2), 0)
+    log("case: the same, two-kernel launch config 1,12,6,2, eta schedule, graph replay")
+    two, _ = _amr3_graph_step(grids, fields, N0, L, (1, 12, 6, 2), 1)
+    for gg, gt in zip(got, two):
+        for x, y in zip(gg, gt):
+            assert np.array_equal(x, y)
     log("  oracle coarse step ...")
     want, dts = O.amr_run(3, N0, L, 4, grids, fields, 1)
     cat_g = [np.concatenate([g[s].ravel() for g in got]) for s in range(8)]
     cat_w = [np.concatenate([w[s].ravel() for w in want]) for s in range(8)]
     err = normwise_errors(cat_g, cat_w)
-    log(f"  errors per field: {err}; dt0 GPU {float(H.dt0.item()):.10e} oracle {dts[0]:.10e}")
-    assert abs(float(H.dt0.item()) - dts[0]) <= 1e-12 * dts[0]
+    log(f"  errors per field: {err}; dt0 GPU {dt0:.10e} oracle {dts[0]:.10e}")
+    assert abs(dt0 - dts[0]) <= 1e-12 * dts[0]
     assert np.all(err <= 1e-10), err
 
 
@@ -59,9 +71,9 @@ def test_amr3_full_size_graph_replay_matches_oracle():
 def test_single128_full_size_matches_oracle(dtype, tol):
     n = (128, 128, 128)
     ic = I.smooth_mhd(3, n, seed=2, v_rms=0.1, b_rms=0.3, jump=True)
-    log(f"case: single grid 128^3 {dtype}, band 4 step pair, launch config 1,8,2")
+    log(f"case: single grid 128^3 {dtype}, band 4 step pair, launch config 1,32,10")
     H = A.Hierarchy(3, n, [(0, (0, 0, 0), n)], ghost=4, dtype=dtype, dx0=ic["dx"], gamma=GAMMA, cfl=0.4)
-    H.set_launch_config(1, 8, 2)
+    H.set_launch_config(1, 32, 10)
     U, V = H.new_state(), H.new_state()
     H.load_primitive(U, 0, ic["prim"], ic["b"])
     want, dts = O.uniform_run(ic, GAMMA, 0.4, 2, g=4, fill_every=2)
