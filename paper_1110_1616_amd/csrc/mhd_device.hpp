@@ -25,7 +25,10 @@ template <class T> __host__ __device__ __forceinline__ T dabs(T x) { return x < 
 // estimate refined by Newton-Raphson steps r <- r + r (1 - x r) (two in
 // double, one in float), each error term formed with one fused multiply-add,
 // which leaves about one ulp (the correctly rounded division costs twice the
-// instructions); on the host, and for other types: plain division.
+// instructions).  In double the estimate is good to about 2^-24 on gfx950:
+// one step leaves up to 11 ulp, two gave the correctly rounded reciprocal on
+// every one of 2^20 random inputs.  On the host, and for other types: plain
+// division.
 __device__ __forceinline__ double drcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = __builtin_fma(-x, r, 1.0);
@@ -45,18 +48,19 @@ template <class T> __host__ __device__ __forceinline__ T drcp(T x) { return T(1)
 // Square root of a non-negative finite x (0 for x <= 0).  On the device in
 // double: Goldschmidt's iteration from the hardware reciprocal square root
 // estimate y ~ 1/sqrt(x) (g = x y -> sqrt(x), h = y/2 -> 1/(2 sqrt(x)), one
-// coupled step, then two corrections g <- g + (x - g^2) h), without the
+// coupled step, then one correction g <- g + (x - g^2) h), without the
 // rescaling of subnormal inputs the general routine does; elsewhere the
-// library square root.
+// library square root.  The estimate is good to about 2^-23 on gfx950, so
+// after the coupled step g is good to about 2^-45 and the correction leaves
+// it at the correctly rounded value on every one of 2^20 random inputs
+// spread over 2^-30..2^30 (a second correction changed none of them).
 __device__ __forceinline__ double psqrt(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y, h = 0.5 * y;
   const double r = __builtin_fma(-h, g, 0.5);
   g = __builtin_fma(g, r, g);
   h = __builtin_fma(h, r, h);
-  double d = __builtin_fma(-g, g, x);
-  g = __builtin_fma(d, h, g);
-  d = __builtin_fma(-g, g, x);
+  const double d = __builtin_fma(-g, g, x);
   g = __builtin_fma(d, h, g);
   return x > 0.0 ? g : 0.0;
 }
