@@ -25,29 +25,38 @@ double time_cycles(amr_hierarchy* h, amr_state* Ua, amr_state* Ub, uint32_t pari
       if (c % span == 0 && (c / span) % R == 0) do_fill<T>(h, l, AMR_FILL_FULL, cur(l), cur(l - 1), s);
     }
   };
-  std::vector<hipEvent_t> ev(2 * (size_t)ncyc * reps);
-  for (hipEvent_t& e : ev) HIPCHK(hipEventCreate(&e));
-  const bool timing = h->timing;
+  // events and the per-kernel timing switch are restored on every exit
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() {
+      for (hipEvent_t e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } ev;
+  ev.v.assign(2 * (size_t)ncyc * reps, nullptr);
+  for (hipEvent_t& e : ev.v) HIPCHK(hipEventCreate(&e));
+  struct KeepTiming {
+    amr_hierarchy* h;
+    bool on;
+    ~KeepTiming() { h->timing = on; }
+  } keep{h, h->timing};
   h->timing = false;
   for (int c = 0; c < ncyc; ++c) run_list<T>(h, h->cycle_lists[c], Ua, Ub, parity, dt0, ws, s);  // warm-up
   size_t n = 0;
   for (int r = 0; r < reps; ++r)
     for (int c = 0; c < ncyc; ++c, n += 2) {
       fills(c);
-      HIPCHK(hipEventRecord(ev[n], s));
+      HIPCHK(hipEventRecord(ev.v[n], s));
       run_list<T>(h, h->cycle_lists[c], Ua, Ub, parity, dt0, ws, s);
-      HIPCHK(hipEventRecord(ev[n + 1], s));
+      HIPCHK(hipEventRecord(ev.v[n + 1], s));
     }
-  h->timing = timing;
+  HIPCHK(hipEventSynchronize(ev.v.back()));
   double ms = 0.0;
-  hipError_t err = hipEventSynchronize(ev.back());
-  for (size_t i = 0; err == hipSuccess && i < n; i += 2) {
+  for (size_t i = 0; i < n; i += 2) {
     float t = 0.f;
-    err = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    HIPCHK(hipEventElapsedTime(&t, ev.v[i], ev.v[i + 1]));
     ms += t;
   }
-  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  HIPCHK(err);
   return ms;
 }
 
