@@ -618,8 +618,11 @@ void check_nesting(amr_hierarchy* h) {
     LevelIndex PI;
     PI.build(h, l - 1);
     const int buf = h->g / h->R + 1;
-    for (int gi : h->level_grids[l]) {
-      const amr_grid& G = h->grids[gi];
+    // grids checked on worker threads; the lowest failing grid is reported
+    const std::vector<int>& lg = h->level_grids[l];
+    std::vector<char> bad(lg.size(), 0);
+    parallel_for(lg.size(), [&](size_t t) {
+      const amr_grid& G = h->grids[lg[t]];
       int lo[3], hi[3];
       for (int a = 0; a < 3; ++a) {
         lo[a] = a < nd ? G.lo[a] / h->R - buf : 0;
@@ -630,10 +633,14 @@ void check_nesting(amr_hierarchy* h) {
         for (int j = lo[1]; j < hi[1]; ++j)
           for (int i = lo[0]; i < hi[0]; ++i) {
             int c[3] = {i, j, k};
-            if (!PI.wrap(c) || PI.find_cell(c, memo) < 0)
-              throw Error(AMR_EINVAL, "grid " + std::to_string(gi) + " violates proper nesting");
+            if (!PI.wrap(c) || PI.find_cell(c, memo) < 0) {
+              bad[t] = 1;
+              return;
+            }
           }
-    }
+    });
+    for (size_t t = 0; t < lg.size(); ++t)
+      if (bad[t]) throw Error(AMR_EINVAL, "grid " + std::to_string(lg[t]) + " violates proper nesting");
   }
   // no overlap within a level
   for (int l = 0; l < h->nlev; ++l) {

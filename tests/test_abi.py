@@ -91,6 +91,10 @@ def test_validate_rejects_broken_nesting():
     grids = [(0, (0, 0, 0), (8, 16, 16)), (1, (4, 4, 4), (12, 12, 12))]
     with pytest.raises(A.AmrError):
         A.amr_validate(p, A.make_grids(grids))
+    # two offending fine grids (checked on worker threads): the lower id is named
+    grids = [(0, (0, 0, 0), (8, 16, 16)), (1, (20, 4, 4), (28, 12, 12)), (1, (4, 4, 4), (12, 12, 12))]
+    with pytest.raises(A.AmrError, match="grid 1 violates proper nesting"):
+        A.amr_validate(p, A.make_grids(grids))
     # band narrower than 2R
     p2 = A.make_params(3, (16, 16, 16), nlevels=2, ghost=2)
     with pytest.raises(A.AmrError):
